@@ -1,0 +1,637 @@
+// Host side of the Downstream tracking + vertexing library: the C ABI of
+// include/ds.h, argument validation, launch configuration and the three
+// launch modes (one launch per event, one persistent work-stealing launch,
+// or that launch replayed from a cached hipGraph).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ds.h"
+#include "ds_kernels.h"
+
+namespace {
+
+constexpr int MAX_STREAM_SLOTS = 64;
+constexpr int MAX_GRAPHS = 64;
+constexpr int VTX_PPT = 4;
+constexpr size_t LDS_LIMIT = 160 * 1024 - 256;   // gfx950: 160 KiB per workgroup, minus static use
+constexpr float PRESCREEN_MARGIN = 0.1f;         // mm, see the float32 error bound of the pair prescreen
+
+struct Launch {
+    int block, wg_per_cu, bins;
+};
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+};
+
+}  // namespace
+
+struct ds_ctx {
+    int device = 0;
+    int n_cu = 256;
+    bool loaded = false;
+    ds::DevGeom G{};
+    double u_min = -1000.0, u_max = 1000.0;
+    double ghost_threshold = 0.5;
+    float *d_W = nullptr;
+    int *d_counters = nullptr;  // [MAX_STREAM_SLOTS][4]
+    std::map<void *, int> slots;
+    Launch trk{256, 4, 512};
+    Launch vtx{256, 4, 0};
+    hipStream_t capture = nullptr;
+    std::map<std::string, GraphEntry> graphs;
+    uint64_t tick = 0;
+    std::mutex mu;
+};
+
+namespace {
+
+ds_status dev_err(hipError_t e) { return e == hipSuccess ? DS_OK : DS_E_DEVICE; }
+
+size_t round16(size_t v) { return (v + 15) & ~size_t(15); }
+
+size_t track_lds(int hcap, int nb) { return round16((size_t)hcap * 6) + (size_t)(4 * nb + 1) * 4; }
+
+size_t vertex_lds(int tcap, int block) { return (size_t)tcap * 24 + (size_t)block * VTX_PPT * 24; }
+
+int round_up(int v, int m) { return ((v + m - 1) / m) * m; }
+
+ds_status slot_for(ds_ctx *c, void *stream, int **counters)
+{
+    auto it = c->slots.find(stream);
+    int s;
+    if (it == c->slots.end()) {
+        if ((int)c->slots.size() >= MAX_STREAM_SLOTS) return DS_E_CAPACITY;
+        s = (int)c->slots.size();
+        c->slots[stream] = s;
+    } else {
+        s = it->second;
+    }
+    *counters = c->d_counters + 4 * s;
+    return DS_OK;
+}
+
+ds_status check_events(const ds_events *ev)
+{
+    if (!ev) return DS_E_ARG;
+    if (ev->n_events < 0 || ev->n_seeds < 0 || ev->n_hits < 0 || ev->max_seeds_per_event < 0 ||
+        ev->max_hits_per_event < 0)
+        return DS_E_ARG;
+    if (ev->n_events == 0) return DS_OK;
+    if (!ev->seed_off || !ev->hit_off) return DS_E_ARG;
+    if (ev->n_seeds > 0 && (!ev->sx || !ev->sy || !ev->stx || !ev->sty || !ev->sqop)) return DS_E_ARG;
+    if (ev->n_hits > 0 && !ev->hu) return DS_E_ARG;
+    return DS_OK;
+}
+
+ds_status check_tracks(const ds_tracks *t, int n_seeds, bool need_score)
+{
+    if (!t || !t->flags) return DS_E_ARG;
+    if (n_seeds == 0) return DS_OK;
+    if (!t->x || !t->y || !t->tx || !t->ty || !t->qop || !t->chi2 || !t->nhits) return DS_E_ARG;
+    for (int L = 0; L < 4; ++L)
+        if (!t->hit[L]) return DS_E_ARG;
+    if (need_score && !t->score) return DS_E_ARG;
+    return DS_OK;
+}
+
+template <typename K>
+void append_bytes(std::string &key, const K &v)
+{
+    key.append(reinterpret_cast<const char *>(&v), sizeof(K));
+}
+
+// ---------------------------------------------------------------- kernels
+
+template <int B>
+hipError_t launch_track_b(const ds::TrackArgs &a, const ds::DevGeom &G, int grid, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL(ds::k_track<B>, dim3(grid), dim3(B), lds, s, a, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_track(int block, const ds::TrackArgs &a, const ds::DevGeom &G, int grid, size_t lds,
+                        hipStream_t s)
+{
+    switch (block) {
+    case 64: return launch_track_b<64>(a, G, grid, lds, s);
+    case 128: return launch_track_b<128>(a, G, grid, lds, s);
+    case 256: return launch_track_b<256>(a, G, grid, lds, s);
+    default: return launch_track_b<512>(a, G, grid, lds, s);
+    }
+}
+
+template <int B>
+hipError_t launch_vertex_b(const ds::VertexArgs &a, const ds::DevGeom &G, int grid, size_t lds, hipStream_t s)
+{
+    hipLaunchKernelGGL((ds::k_vertex<B, VTX_PPT>), dim3(grid), dim3(B), lds, s, a, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_vertex(int block, const ds::VertexArgs &a, const ds::DevGeom &G, int grid, size_t lds,
+                         hipStream_t s)
+{
+    switch (block) {
+    case 64: return launch_vertex_b<64>(a, G, grid, lds, s);
+    case 128: return launch_vertex_b<128>(a, G, grid, lds, s);
+    case 256: return launch_vertex_b<256>(a, G, grid, lds, s);
+    default: return launch_vertex_b<512>(a, G, grid, lds, s);
+    }
+}
+
+// Allow every instantiation the full LDS of a gfx950 workgroup.
+hipError_t set_kernel_attributes()
+{
+    const void *fns[] = {
+        reinterpret_cast<const void *>(&ds::k_track<64>), reinterpret_cast<const void *>(&ds::k_track<128>),
+        reinterpret_cast<const void *>(&ds::k_track<256>), reinterpret_cast<const void *>(&ds::k_track<512>),
+        reinterpret_cast<const void *>(&ds::k_vertex<64, VTX_PPT>),
+        reinterpret_cast<const void *>(&ds::k_vertex<128, VTX_PPT>),
+        reinterpret_cast<const void *>(&ds::k_vertex<256, VTX_PPT>),
+        reinterpret_cast<const void *>(&ds::k_vertex<512, VTX_PPT>)};
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_LIMIT);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// A prepared launch: arguments, shape, and the per-event variant.
+struct TrackPlan {
+    ds::TrackArgs a;
+    int block, grid;
+    size_t lds;
+};
+
+struct VertexPlan {
+    ds::VertexArgs a;
+    int block, grid;
+    size_t lds;
+};
+
+ds_status plan_track(ds_ctx *c, const ds_events *ev, const ds_tracks *out, int fuse, int *counters, TrackPlan *p)
+{
+    const int nb = c->trk.bins;
+    int hcap = round_up(std::max(ev->max_hits_per_event, 1), 64);
+    size_t lds = track_lds(hcap, nb);
+    if (lds > LDS_LIMIT) return DS_E_CAPACITY;
+    ds::TrackArgs &a = p->a;
+    std::memset(&a, 0, sizeof(a));
+    a.n_events = ev->n_events;
+    a.n_seeds = ev->n_seeds;
+    a.n_hits = ev->n_hits;
+    a.max_seeds = ev->max_seeds_per_event;
+    a.max_hits = ev->max_hits_per_event;
+    a.seed_off = ev->seed_off;
+    a.sx = ev->sx;
+    a.sy = ev->sy;
+    a.stx = ev->stx;
+    a.sty = ev->sty;
+    a.sqop = ev->sqop;
+    a.hit_off = ev->hit_off;
+    a.hu = ev->hu;
+    a.x = out->x;
+    a.y = out->y;
+    a.tx = out->tx;
+    a.ty = out->ty;
+    a.qop = out->qop;
+    a.chi2 = out->chi2;
+    a.score = out->score;
+    a.h0 = out->hit[0];
+    a.h1 = out->hit[1];
+    a.h2 = out->hit[2];
+    a.h3 = out->hit[3];
+    a.nhits = out->nhits;
+    a.cand = out->cand;
+    a.flags = out->flags;
+    a.counter = counters;
+    a.W = c->d_W;
+    a.fuse_mlp = fuse ? 1 : 0;
+    a.ev_single = -1;
+    a.hcap = hcap;
+    a.nb = nb;
+    a.u0 = (float)c->u_min;
+    a.inv_bw = (float)((double)nb / (c->u_max - c->u_min));
+    p->block = c->trk.block;
+    p->grid = std::max(1, std::min(ev->n_events, c->n_cu * c->trk.wg_per_cu));
+    p->lds = lds;
+    return DS_OK;
+}
+
+ds_status plan_vertex(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, float score_max, const ds_vertices *out,
+                      int *counters, VertexPlan *p)
+{
+    int tcap = round_up(std::max(ev->max_seeds_per_event, 1), 64);
+    if (tcap > 65535) return DS_E_CAPACITY;
+    size_t lds = vertex_lds(tcap, c->vtx.block);
+    if (lds > LDS_LIMIT) return DS_E_CAPACITY;
+    ds::VertexArgs &a = p->a;
+    std::memset(&a, 0, sizeof(a));
+    a.n_events = ev->n_events;
+    a.n_seeds = ev->n_seeds;
+    a.max_seeds = ev->max_seeds_per_event;
+    a.seed_off = ev->seed_off;
+    a.sqop = ev->sqop;
+    a.x = trk->x;
+    a.y = trk->y;
+    a.tx = trk->tx;
+    a.ty = trk->ty;
+    a.qop = trk->qop;
+    a.score = trk->score;
+    a.nhits = trk->nhits;
+    a.score_max = score_max;
+    a.cap = out->cap_per_event;
+    a.count = out->count;
+    a.vi = out->i;
+    a.vj = out->j;
+    a.vx = out->x;
+    a.vy = out->y;
+    a.vz = out->z;
+    a.vdoca = out->doca;
+    a.overflow = out->overflow;
+    a.flags = out->flags;
+    a.counter = counters + 2;
+    a.ev_single = -1;
+    a.tcap = tcap;
+    p->block = c->vtx.block;
+    p->grid = std::max(1, std::min(ev->n_events, c->n_cu * c->vtx.wg_per_cu));
+    p->lds = lds;
+    return DS_OK;
+}
+
+hipError_t run_track(ds_ctx *c, const TrackPlan &p, int mode, hipStream_t s)
+{
+    if (mode == DS_MODE_PER_EVENT) {
+        ds::TrackArgs a = p.a;
+        for (int e = 0; e < a.n_events; ++e) {
+            a.ev_single = e;
+            hipError_t err = launch_track(p.block, a, c->G, 1, p.lds, s);
+            if (err != hipSuccess) return err;
+        }
+        return hipSuccess;
+    }
+    return launch_track(p.block, p.a, c->G, p.grid, p.lds, s);
+}
+
+hipError_t run_vertex(ds_ctx *c, const VertexPlan &p, int mode, hipStream_t s)
+{
+    if (mode == DS_MODE_PER_EVENT) {
+        ds::VertexArgs a = p.a;
+        for (int e = 0; e < a.n_events; ++e) {
+            a.ev_single = e;
+            hipError_t err = launch_vertex(p.block, a, c->G, 1, p.lds, s);
+            if (err != hipSuccess) return err;
+        }
+        return hipSuccess;
+    }
+    return launch_vertex(p.block, p.a, c->G, p.grid, p.lds, s);
+}
+
+// Run `body` (which enqueues persistent launches on the given stream) either
+// directly or through a hipGraph cached under `key`.
+template <typename F>
+ds_status run_maybe_graph(ds_ctx *c, int mode, const std::string &key, hipStream_t s, F body)
+{
+    if (mode != DS_MODE_GRAPH) return dev_err(body(s));
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        if ((int)c->graphs.size() >= MAX_GRAPHS) {
+            auto victim = c->graphs.begin();
+            for (auto g = c->graphs.begin(); g != c->graphs.end(); ++g)
+                if (g->second.last_use < victim->second.last_use) victim = g;
+            (void)hipGraphExecDestroy(victim->second.exec);
+            (void)hipGraphDestroy(victim->second.graph);
+            c->graphs.erase(victim);
+        }
+        GraphEntry ge;
+        hipError_t err = hipStreamBeginCapture(c->capture, hipStreamCaptureModeRelaxed);
+        if (err != hipSuccess) return DS_E_DEVICE;
+        hipError_t berr = body(c->capture);
+        err = hipStreamEndCapture(c->capture, &ge.graph);
+        if (berr != hipSuccess || err != hipSuccess) {
+            if (ge.graph) (void)hipGraphDestroy(ge.graph);
+            return DS_E_DEVICE;
+        }
+        err = hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0);
+        if (err != hipSuccess) {
+            (void)hipGraphDestroy(ge.graph);
+            return DS_E_DEVICE;
+        }
+        it = c->graphs.emplace(key, ge).first;
+    }
+    it->second.last_use = ++c->tick;
+    return dev_err(hipGraphLaunch(it->second.exec, s));
+}
+
+std::string graph_key(int kind, const void *args, size_t n, int block, int grid, size_t lds)
+{
+    std::string key;
+    append_bytes(key, kind);
+    key.append(reinterpret_cast<const char *>(args), n);
+    append_bytes(key, block);
+    append_bytes(key, grid);
+    append_bytes(key, lds);
+    return key;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ds_status_str(ds_status s)
+{
+    switch (s) {
+    case DS_OK: return "DS_OK";
+    case DS_E_ARG: return "DS_E_ARG: invalid argument";
+    case DS_E_STATE: return "DS_E_STATE: geometry not loaded";
+    case DS_E_NOMEM: return "DS_E_NOMEM: allocation failed";
+    case DS_E_CAPACITY: return "DS_E_CAPACITY: size beyond library capacity";
+    case DS_E_DEVICE: return "DS_E_DEVICE: HIP runtime error";
+    }
+    return "unknown ds_status";
+}
+
+ds_status ds_create(ds_ctx **ctx, int device)
+{
+    if (!ctx) return DS_E_ARG;
+    *ctx = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return DS_E_ARG;
+    if (hipSetDevice(device) != hipSuccess) return DS_E_DEVICE;
+    ds_ctx *c = new (std::nothrow) ds_ctx();
+    if (!c) return DS_E_NOMEM;
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->n_cu = prop.multiProcessorCount;
+    if (hipMalloc(&c->d_counters, sizeof(int) * 4 * MAX_STREAM_SLOTS) != hipSuccess) {
+        delete c;
+        return DS_E_NOMEM;
+    }
+    if (set_kernel_attributes() != hipSuccess ||
+        hipMemset(c->d_counters, 0, sizeof(int) * 4 * MAX_STREAM_SLOTS) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipFree(c->d_counters);
+        delete c;
+        return DS_E_DEVICE;
+    }
+    *ctx = c;
+    return DS_OK;
+}
+
+void ds_destroy(ds_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    for (auto &g : c->graphs) {
+        (void)hipGraphExecDestroy(g.second.exec);
+        (void)hipGraphDestroy(g.second.graph);
+    }
+    if (c->d_W) (void)hipFree(c->d_W);
+    if (c->d_counters) (void)hipFree(c->d_counters);
+    if (c->capture) (void)hipStreamDestroy(c->capture);
+    delete c;
+}
+
+ds_status ds_load_geometry(ds_ctx *c, const ds_geometry *g, const float *w, size_t nw)
+{
+    if (!c || !g || !w || nw != (size_t)ds::NWEIGHTS) return DS_E_ARG;
+    if (g->max_l3 < 0 || g->max_l3 > ds::MAX_L3 || g->newton_iters < 0 || g->newton_iters > 16) return DS_E_ARG;
+    for (int L = 0; L < 3; ++L)
+        if (g->n_closest[L] < 0 || g->n_closest[L] > ds::MAX_CLOSEST) return DS_E_ARG;
+    if (!(g->u_max > g->u_min) || !(g->sigma_hit > 0.0) || g->z_magnet == g->z_layer[3]) return DS_E_ARG;
+    for (int L = 0; L < 3; ++L)
+        if (!(g->z_layer[L] < g->z_layer[L + 1])) return DS_E_ARG;
+    std::lock_guard<std::mutex> lock(c->mu);
+    if (hipSetDevice(c->device) != hipSuccess) return DS_E_DEVICE;
+    ds::DevGeom G{};
+    for (int L = 0; L < 4; ++L) {
+        G.zl[L] = g->z_layer[L];
+        G.tana[L] = g->tan_stereo[L];
+        G.dz[L] = g->z_layer[L] - g->z_ref;
+    }
+    G.zm = g->z_magnet;
+    G.zs = g->z_seed;
+    G.zref = g->z_ref;
+    G.mk = g->polarity * g->kick;
+    G.inv_sigma2 = 1.0 / (g->sigma_hit * g->sigma_hit);
+    G.inv_5sigma = 1.0 / (5.0 * g->sigma_hit);
+    G.w1c0 = g->w1_c0;
+    G.w1c1 = g->w1_c1;
+    G.w2c0 = g->w2_c0;
+    G.w2c1 = g->w2_c1;
+    for (int L = 0; L < 3; ++L) G.ffac[L] = (g->z_magnet - g->z_layer[L]) / (g->z_magnet - g->z_layer[3]);
+    const int masks[4] = {11, 13, 14, 15};
+    for (int k = 0; k < 4; ++k) {
+        double n = 0, sz = 0, szz = 0;
+        for (int L = 0; L < 4; ++L)
+            if ((masks[k] >> L) & 1) {
+                n += 1;
+                sz += G.dz[L];
+                szz += G.dz[L] * G.dz[L];
+            }
+        G.fit_sz[k] = sz;
+        G.fit_inv_det[k] = 1.0 / (n * szz - sz * sz);
+        G.fit_inv_n[k] = 1.0 / n;
+    }
+    G.zm_ref = g->z_magnet - g->z_ref;
+    G.zm_seed = g->z_magnet - g->z_seed;
+    G.zref_seed = g->z_ref - g->z_seed;
+    G.gc0 = g->gamma_c0;
+    G.gc1 = g->gamma_c1;
+    G.fp = g->fringe_polarity;
+    G.doca_max = g->doca_max;
+    const float thr = (float)g->doca_max + PRESCREEN_MARGIN;
+    G.prescreen_thr2 = thr * thr;
+    G.max_l3 = g->max_l3;
+    for (int L = 0; L < 3; ++L) {
+        G.ncl[L] = g->n_closest[L];
+        G.nw[L] = std::max(g->n_closest[L], 1);
+    }
+    G.newton_iters = g->newton_iters;
+    if (!c->d_W && hipMalloc(&c->d_W, sizeof(float) * ds::NWEIGHTS) != hipSuccess) return DS_E_NOMEM;
+    if (hipMemcpy(c->d_W, w, sizeof(float) * ds::NWEIGHTS, hipMemcpyHostToDevice) != hipSuccess)
+        return DS_E_DEVICE;
+    c->G = G;
+    c->u_min = g->u_min;
+    c->u_max = g->u_max;
+    c->ghost_threshold = g->ghost_threshold;
+    // cached graphs hold the old geometry as kernel arguments
+    for (auto &e : c->graphs) {
+        (void)hipGraphExecDestroy(e.second.exec);
+        (void)hipGraphDestroy(e.second.graph);
+    }
+    c->graphs.clear();
+    c->loaded = true;
+    return DS_OK;
+}
+
+ds_status ds_find_tracks(ds_ctx *c, const ds_events *ev, const ds_tracks *out, int mode, int fuse, void *stream)
+{
+    if (!c) return DS_E_ARG;
+    if (!c->loaded) return DS_E_STATE;
+    if (mode < DS_MODE_PER_EVENT || mode > DS_MODE_GRAPH) return DS_E_ARG;
+    ds_status st = check_events(ev);
+    if (st != DS_OK) return st;
+    st = check_tracks(out, ev->n_seeds, fuse != 0);
+    if (st != DS_OK) return st;
+    if (ev->n_events == 0) return DS_OK;
+    std::lock_guard<std::mutex> lock(c->mu);
+    if (hipSetDevice(c->device) != hipSuccess) return DS_E_DEVICE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int *counters;
+    st = slot_for(c, stream, &counters);
+    if (st != DS_OK) return st;
+    TrackPlan p;
+    st = plan_track(c, ev, out, fuse, counters, &p);
+    if (st != DS_OK) return st;
+    std::string key = graph_key(0, &p.a, sizeof(p.a), p.block, p.grid, p.lds);
+    return run_maybe_graph(c, mode, key, s, [&](hipStream_t ss) { return run_track(c, p, mode, ss); });
+}
+
+ds_status ds_ghost_kill(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, void *stream)
+{
+    if (!c) return DS_E_ARG;
+    if (!c->loaded) return DS_E_STATE;
+    ds_status st = check_events(ev);
+    if (st != DS_OK) return st;
+    st = check_tracks(trk, ev->n_seeds, true);
+    if (st != DS_OK) return st;
+    if (ev->n_events == 0) return DS_OK;
+    std::lock_guard<std::mutex> lock(c->mu);
+    if (hipSetDevice(c->device) != hipSuccess) return DS_E_DEVICE;
+    ds::GhostArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.n_events = ev->n_events;
+    a.n_seeds = ev->n_seeds;
+    a.n_hits = ev->n_hits;
+    a.seed_off = ev->seed_off;
+    a.sx = ev->sx;
+    a.sy = ev->sy;
+    a.stx = ev->stx;
+    a.sty = ev->sty;
+    a.sqop = ev->sqop;
+    a.hit_off = ev->hit_off;
+    a.hu = ev->hu;
+    a.x = trk->x;
+    a.y = trk->y;
+    a.tx = trk->tx;
+    a.ty = trk->ty;
+    a.qop = trk->qop;
+    a.chi2 = trk->chi2;
+    a.h0 = trk->hit[0];
+    a.h1 = trk->hit[1];
+    a.h2 = trk->hit[2];
+    a.h3 = trk->hit[3];
+    a.nhits = trk->nhits;
+    a.score = trk->score;
+    a.flags = trk->flags;
+    a.W = c->d_W;
+    const int grid = std::max(1, std::min(ev->n_events, c->n_cu * 8));
+    hipLaunchKernelGGL(ds::k_ghost<128>, dim3(grid), dim3(128), 0, reinterpret_cast<hipStream_t>(stream), a, c->G);
+    return dev_err(hipGetLastError());
+}
+
+ds_status ds_vertex(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, float score_max, const ds_vertices *out,
+                    int mode, void *stream)
+{
+    if (!c) return DS_E_ARG;
+    if (!c->loaded) return DS_E_STATE;
+    if (mode < DS_MODE_PER_EVENT || mode > DS_MODE_GRAPH) return DS_E_ARG;
+    ds_status st = check_events(ev);
+    if (st != DS_OK) return st;
+    st = check_tracks(trk, ev->n_seeds, true);
+    if (st != DS_OK) return st;
+    if (!out || out->cap_per_event < 0 || !out->overflow || !out->flags) return DS_E_ARG;
+    if (ev->n_events == 0) return DS_OK;
+    if (!out->count) return DS_E_ARG;
+    if (out->cap_per_event > 0 && (!out->i || !out->j || !out->x || !out->y || !out->z || !out->doca))
+        return DS_E_ARG;
+    std::lock_guard<std::mutex> lock(c->mu);
+    if (hipSetDevice(c->device) != hipSuccess) return DS_E_DEVICE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int *counters;
+    st = slot_for(c, stream, &counters);
+    if (st != DS_OK) return st;
+    VertexPlan p;
+    st = plan_vertex(c, ev, trk, score_max, out, counters, &p);
+    if (st != DS_OK) return st;
+    std::string key = graph_key(1, &p.a, sizeof(p.a), p.block, p.grid, p.lds);
+    return run_maybe_graph(c, mode, key, s, [&](hipStream_t ss) { return run_vertex(c, p, mode, ss); });
+}
+
+ds_status ds_process(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, float score_max, const ds_vertices *out,
+                     int mode, void *stream)
+{
+    if (!c) return DS_E_ARG;
+    if (!c->loaded) return DS_E_STATE;
+    if (mode < DS_MODE_PER_EVENT || mode > DS_MODE_GRAPH) return DS_E_ARG;
+    ds_status st = check_events(ev);
+    if (st != DS_OK) return st;
+    st = check_tracks(trk, ev->n_seeds, true);
+    if (st != DS_OK) return st;
+    if (!out || out->cap_per_event < 0 || !out->overflow || !out->flags) return DS_E_ARG;
+    if (ev->n_events == 0) return DS_OK;
+    if (!out->count) return DS_E_ARG;
+    if (out->cap_per_event > 0 && (!out->i || !out->j || !out->x || !out->y || !out->z || !out->doca))
+        return DS_E_ARG;
+    if (std::isnan(score_max)) score_max = (float)c->ghost_threshold;
+    std::lock_guard<std::mutex> lock(c->mu);
+    if (hipSetDevice(c->device) != hipSuccess) return DS_E_DEVICE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int *counters;
+    st = slot_for(c, stream, &counters);
+    if (st != DS_OK) return st;
+    TrackPlan tp;
+    st = plan_track(c, ev, trk, 1, counters, &tp);
+    if (st != DS_OK) return st;
+    VertexPlan vp;
+    st = plan_vertex(c, ev, trk, score_max, out, counters, &vp);
+    if (st != DS_OK) return st;
+    std::string key = graph_key(2, &tp.a, sizeof(tp.a), tp.block, tp.grid, tp.lds);
+    key += graph_key(3, &vp.a, sizeof(vp.a), vp.block, vp.grid, vp.lds);
+    return run_maybe_graph(c, mode, key, s, [&](hipStream_t ss) {
+        hipError_t e = run_track(c, tp, mode, ss);
+        if (e != hipSuccess) return e;
+        return run_vertex(c, vp, mode, ss);
+    });
+}
+
+ds_status ds_set_launch(ds_ctx *c, int kernel, int block, int wg_per_cu, int bins)
+{
+    if (!c || (kernel != 0 && kernel != 1)) return DS_E_ARG;
+    if (block != 0 && block != 64 && block != 128 && block != 256 && block != 512) return DS_E_ARG;
+    if (wg_per_cu < 0 || wg_per_cu > 16) return DS_E_ARG;
+    if (bins != 0 && (kernel != 0 || bins < 64 || bins > 4096 || (bins & (bins - 1)))) return DS_E_ARG;
+    std::lock_guard<std::mutex> lock(c->mu);
+    Launch &L = kernel == 0 ? c->trk : c->vtx;
+    Launch n = L;
+    if (block) n.block = block;
+    if (wg_per_cu) n.wg_per_cu = wg_per_cu;
+    if (bins) n.bins = bins;
+    if (kernel == 0 && (4 * n.bins) % n.block != 0) return DS_E_ARG;
+    L = n;
+    return DS_OK;
+}
+
+ds_status ds_get_launch(ds_ctx *c, int kernel, int *block, int *wg_per_cu, int *bins)
+{
+    if (!c || (kernel != 0 && kernel != 1) || !block || !wg_per_cu || !bins) return DS_E_ARG;
+    std::lock_guard<std::mutex> lock(c->mu);
+    const Launch &L = kernel == 0 ? c->trk : c->vtx;
+    *block = L.block;
+    *wg_per_cu = L.wg_per_cu;
+    *bins = L.bins;
+    return DS_OK;
+}
+
+}  // extern "C"

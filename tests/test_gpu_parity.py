@@ -1,0 +1,310 @@
+"""HIP path vs the FP64 oracle, element by element, through the C ABI.
+
+Sizes: configs 0-5 on subsets the oracle finishes in seconds (several
+workgroup tiles and ragged tails), the loose-window mode, kick/polarity
+variants, the curved-trajectory vertexer, edge cases, and the full 10 000
+event throughput batch in the launch configuration the benchmark times
+(checked on a sample of events).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import pyoracle as O
+from paper_2503_13092_amd import synth
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2503_13092_amd import ds  # noqa: E402
+
+W = synth.mlp_weights()
+G0 = synth.default_geometry()
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = ds.Context(0, G0, W)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def gpu_run(ctx_h, batch, mode=ds.DS_MODE_PERSISTENT, fuse=1, score_max=None, cap=1024, g=G0, vertex=True,
+            max_hits=None, max_seeds=None):
+    ev = ds.DeviceEvents(batch, max_hits_per_event=max_hits, max_seeds_per_event=max_seeds)
+    tr = ds.DeviceTracks(batch.n_seeds)
+    vt = ds.DeviceVertices(batch.n_events, cap)
+    ds.ds_find_tracks(ctx_h, ev, tr, mode, fuse)
+    if not fuse:
+        ds.ds_ghost_kill(ctx_h, ev, tr)
+    if vertex:
+        sm = g["ghost_threshold"] if score_max is None else score_max
+        ds.ds_vertex(ctx_h, ev, tr, sm, vt, mode)
+    torch.cuda.synchronize()
+    return tr.to_numpy(), (vt.to_numpy() if vertex else None)
+
+
+def check_path(ctx_h, batch, g=G0, score_max=None, mode=ds.DS_MODE_PERSISTENT, label=""):
+    say(f"[parity] {label}: {batch.n_events} events, {batch.n_seeds} seeds, {batch.n_hits} hits, mode {mode}")
+    gt, gv = gpu_run(ctx_h, batch, mode=mode, score_max=score_max, g=g)
+    sm = g["ghost_threshold"] if score_max is None else score_max
+    ref = O.run_path(batch, g, W, score_max=sm, cap=1024, n_threads=8)
+    tc = parity.compare_tracks(gt, ref["tracks"])
+    found = ref["tracks"]["nhits"] > 0
+    sc = parity.compare_scores(gt["score"], ref["score"], found & (gt["nhits"] == ref["tracks"]["nhits"]),
+                               threshold=sm if math.isfinite(sm) else 0.5)
+    vc = parity.compare_vertices(gv, ref["vertices"], g["doca_max"], parity.excused_slot_set(batch, tc, sc))
+    assert gt["flags"] == 0 and gv["flags"] == 0
+    say(f"[parity] {label}: identical {tc['identical']}/{tc['n']} (excused {len(tc['excused'])}), "
+        f"found {tc['found']}, worst {tc['worst']}, score err {sc['worst']:.2e}, vertices {vc['n_gpu']}/{vc['n_ref']}")
+    return gt, gv, ref
+
+
+def test_config0_full(ctx):
+    b = synth.generate(0)
+    check_path(ctx.handle, b, label="config0")
+
+
+@pytest.mark.parametrize("config,n", [(1, 300), (2, 400), (4, 60), (5, 8)])
+def test_configs_subsets(ctx, config, n):
+    b = synth.generate(config, n_events=n)
+    sm = math.inf if config in (4, 5) else None
+    check_path(ctx.handle, b, score_max=sm, label=f"config{config}x{n}")
+
+
+def test_loose_windows_hit_the_caps(ctx):
+    g = synth.default_geometry(loose=True)
+    c = ds.Context(0, g, W)
+    try:
+        b = synth.generate(1, n_events=40, geometry=g)
+        gt, _, ref = check_path(c.handle, b, g=g, label="loose")
+        assert np.max(ref["tracks"]["cand"]) >= 36  # the 10th UTbX hit was used
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+
+
+@pytest.mark.parametrize("kick,pol", [(1.2, 1.0), (1.2e-3, -1.0), (0.0, 1.0)])
+def test_kick_variants(kick, pol):
+    g = dict(G0, kick=kick, polarity=pol)
+    c = ds.Context(0, g, W)
+    try:
+        b = synth.generate(0, n_events=60, geometry=g, seed=17)
+        check_path(c.handle, b, g=g, score_max=math.inf, label=f"kick{kick}pol{pol}")
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+
+
+def test_launch_modes_bitwise_equal(ctx):
+    b = synth.generate(0, seed=3)
+    outs = [gpu_run(ctx.handle, b, mode=m, score_max=math.inf) for m in (ds.DS_MODE_PER_EVENT,
+                                                                          ds.DS_MODE_PERSISTENT, ds.DS_MODE_GRAPH)]
+    outs.append(gpu_run(ctx.handle, b, mode=ds.DS_MODE_GRAPH, score_max=math.inf))  # graph replay
+    for t, v in outs[1:]:
+        for k in ("x", "y", "tx", "ty", "qop", "chi2", "score", "hits", "nhits", "cand"):
+            assert np.array_equal(t[k], outs[0][0][k]), k
+        for k in ("count", "i", "j", "x", "y", "z", "doca"):
+            assert np.array_equal(v[k], outs[0][1][k]), k
+
+
+def test_standalone_ghost_kill_equals_fused(ctx):
+    b = synth.generate(1, n_events=50, seed=5)
+    fused, _ = gpu_run(ctx.handle, b, fuse=1, vertex=False)
+    alone, _ = gpu_run(ctx.handle, b, fuse=0, vertex=False)
+    assert np.array_equal(fused["score"], alone["score"])
+
+
+def test_process_graph_matches_separate_calls(ctx):
+    b = synth.generate(0, seed=9)
+    t1, v1 = gpu_run(ctx.handle, b, mode=ds.DS_MODE_PERSISTENT)
+    ev = ds.DeviceEvents(b)
+    tr = ds.DeviceTracks(b.n_seeds)
+    vt = ds.DeviceVertices(b.n_events, 1024)
+    for _ in range(3):
+        ds.ds_process(ctx.handle, ev, tr, vt, ds.DS_MODE_GRAPH)
+    torch.cuda.synchronize()
+    t2, v2 = tr.to_numpy(), vt.to_numpy()
+    for k in ("score", "hits", "nhits"):
+        assert np.array_equal(t1[k], t2[k])
+    for k in ("count", "i", "j", "x", "y", "z"):
+        assert np.array_equal(v1[k], v2[k])
+
+
+def test_hit_order_invariance_and_determinism(ctx):
+    b = synth.generate(1, n_events=30, seed=23)
+    t1, v1 = gpu_run(ctx.handle, b, score_max=math.inf)
+    t1b, _ = gpu_run(ctx.handle, b, score_max=math.inf)
+    for k in ("x", "score", "hits", "nhits"):
+        assert np.array_equal(t1[k], t1b[k])
+    rng = np.random.default_rng(1)
+    perm = np.arange(b.n_hits)
+    for k in range(4 * b.n_events):
+        a, c = b.hit_off[k], b.hit_off[k + 1]
+        perm[a:c] = a + rng.permutation(c - a)
+    b2 = synth.EventBatch(b.n_events, b.seed_off, b.sx, b.sy, b.stx, b.sty, b.sqop, b.hit_off, b.hu[perm])
+    t2, v2 = gpu_run(ctx.handle, b2, score_max=math.inf)
+    assert np.array_equal(t1["nhits"], t2["nhits"]) and np.array_equal(t1["score"], t2["score"])
+    for e in range(b.n_events):
+        for i in range(b.seed_off[e], b.seed_off[e + 1]):
+            for L in range(4):
+                h1, h2 = t1["hits"][i, L], t2["hits"][i, L]
+                if h1 < 0:
+                    assert h2 < 0
+                else:
+                    base = b.hit_off[4 * e + L]
+                    assert perm[base + h2] == base + h1
+
+
+def test_vertexer_on_generated_track_states(ctx):
+    """ds_vertex alone: the same float32 track states feed both sides."""
+    s = synth.vertex_track_sample(n_events=40, n_pairs=6, n_random=40, seed=31)
+    n = len(s["x"])
+    E = len(s["seed_off"]) - 1
+    b = synth.EventBatch(E, s["seed_off"], s["x"], s["y"], s["tx"], s["ty"], s["sqop"],
+                         np.zeros(4 * E + 1, np.int32), np.zeros(0, np.float32))
+    ev = ds.DeviceEvents(b)
+    tr = ds.DeviceTracks(n)
+    for k in ("x", "y", "tx", "ty", "qop", "score"):
+        getattr(tr, k).copy_(torch.from_numpy(s[k]))
+    tr.nhits.copy_(torch.from_numpy(s["nhits"]))
+    for fp in (0.0, 1.0, -1.0):
+        g = dict(G0, fringe_polarity=fp)
+        c = ds.Context(0, g, W)
+        try:
+            vt = ds.DeviceVertices(E, 256)
+            ds.ds_vertex(c.handle, ev, tr, math.inf, vt, ds.DS_MODE_PERSISTENT)
+            torch.cuda.synchronize()
+            gv = vt.to_numpy()
+            st = dict(x=s["x"], y=s["y"], tx=s["tx"], ty=s["ty"], qop=s["qop"], nhits=s["nhits"])
+            rv = O.vertex(s["seed_off"], s["sqop"], st, s["score"].astype(np.float64), g, math.inf, 256)
+            vc = parity.compare_vertices(gv, rv, g["doca_max"])
+            say(f"[parity] vertexer fp={fp}: {vc['n_gpu']} vs {vc['n_ref']} vertices")
+            assert vc["n_ref"] >= E * 3
+        finally:
+            torch.cuda.synchronize()
+            c.close()
+
+
+def test_vertex_cap_and_overflow(ctx):
+    s = synth.vertex_track_sample(n_events=5, n_pairs=8, n_random=0, seed=2, smear=0.0)
+    n = len(s["x"])
+    E = 5
+    b = synth.EventBatch(E, s["seed_off"], s["x"], s["y"], s["tx"], s["ty"], s["sqop"],
+                         np.zeros(4 * E + 1, np.int32), np.zeros(0, np.float32))
+    ev = ds.DeviceEvents(b)
+    tr = ds.DeviceTracks(n)
+    for k in ("x", "y", "tx", "ty", "qop", "score"):
+        getattr(tr, k).copy_(torch.from_numpy(s[k]))
+    tr.nhits.copy_(torch.from_numpy(s["nhits"]))
+    vt = ds.DeviceVertices(E, 3)
+    ds.ds_vertex(ctx.handle, ev, tr, math.inf, vt, ds.DS_MODE_PERSISTENT)
+    torch.cuda.synchronize()
+    gv = vt.to_numpy()
+    st = dict(x=s["x"], y=s["y"], tx=s["tx"], ty=s["ty"], qop=s["qop"], nhits=s["nhits"])
+    rv = O.vertex(s["seed_off"], s["sqop"], st, s["score"].astype(np.float64), G0, math.inf, 3)
+    assert list(gv["count"]) == list(rv["count"]) == [3] * E
+    assert gv["overflow"] == rv["overflow"] > 0
+    parity.compare_vertices(gv, rv, G0["doca_max"])
+
+
+def test_edge_cases(ctx):
+    seed = [100.0, 0.0, 0.0, 0.0, 0.25]
+    evs = [dict(seeds=[], hits=[[], [], [], []]),
+           dict(seeds=[seed], hits=[[], [], [], []]),
+           dict(seeds=[], hits=[[1.0], [2.0], [3.0], [4.0]]),
+           dict(seeds=[seed, seed], hits=[[100.0], [100.0, 100.0], [100.0], [100.0, 100.0]]),
+           dict(seeds=[seed], hits=[[100.0], [100.0], [100.0], [float("nan")]]),
+           dict(seeds=[[float("inf"), 0, 0, 0, 0.1]], hits=[[100.0], [100.0], [100.0], [100.0]])]
+    b = synth.batch_from_lists(evs)
+    g = dict(G0, kick=0.0)
+    c = ds.Context(0, g, W)
+    try:
+        gt, gv = gpu_run(c.handle, b, g=g, score_max=math.inf)
+        ref = O.find_tracks(b, g)
+        assert list(gt["nhits"]) == list(ref["nhits"]) == [0, 4, 4, 0, 0]
+        assert np.array_equal(gt["hits"], ref["hits"])
+        assert gt["flags"] == ds.DS_F_NONFINITE
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+
+
+def test_device_side_offset_and_capacity_checks(ctx):
+    b = synth.generate(0, n_events=6)
+    # an event above the declared capacity is flagged and skipped
+    gt, _ = gpu_run(ctx.handle, b, max_hits=1000, vertex=False)
+    assert gt["flags"] & ds.DS_F_CAPACITY and gt["nhits"].sum() == 0
+    # non-monotone offsets: flagged, no write outside the event's seeds
+    bad = synth.EventBatch(b.n_events, b.seed_off.copy(), b.sx, b.sy, b.stx, b.sty, b.sqop, b.hit_off.copy(), b.hu)
+    bad.hit_off[5] = bad.hit_off[3] - 1
+    ev = ds.DeviceEvents(bad, max_hits_per_event=4096, max_seeds_per_event=64)
+    tr = ds.DeviceTracks(bad.n_seeds)
+    ds.ds_find_tracks(ctx.handle, ev, tr, ds.DS_MODE_PERSISTENT, 1)
+    torch.cuda.synchronize()
+    out = tr.to_numpy()
+    assert out["flags"] & ds.DS_F_BAD_OFFSETS
+    assert out["nhits"][b.seed_off[1]:b.seed_off[2]].sum() == 0
+    assert out["nhits"][b.seed_off[2]:].sum() > 0
+
+
+def test_host_argument_errors(ctx):
+    b = synth.generate(0, n_events=2)
+    ev = ds.DeviceEvents(b)
+    tr = ds.DeviceTracks(b.n_seeds)
+    with pytest.raises(ds.DsError) as ei:
+        ds.ds_find_tracks(ctx.handle, ev, tr, 7, 1)
+    assert ei.value.status == ds.DS_E_ARG
+    ev2 = ds.DeviceEvents(b, max_hits_per_event=10 ** 6)
+    with pytest.raises(ds.DsError) as ei:
+        ds.ds_find_tracks(ctx.handle, ev2, tr, ds.DS_MODE_PERSISTENT, 1)
+    assert ei.value.status == ds.DS_E_CAPACITY
+    c2 = ds.Context(0)
+    try:
+        with pytest.raises(ds.DsError) as ei:
+            ds.ds_find_tracks(c2.handle, ev, tr, ds.DS_MODE_PERSISTENT, 1)
+        assert ei.value.status == ds.DS_E_STATE
+    finally:
+        c2.close()
+
+
+def test_full_throughput_batch_sampled(ctx):
+    """The benchmark's 10 000-event batch, in its launch mode (graph-replayed
+    persistent launch); 150 events checked against the oracle."""
+    b = synth.generate(1)
+    ev = ds.DeviceEvents(b)
+    tr = ds.DeviceTracks(b.n_seeds)
+    vt = ds.DeviceVertices(b.n_events, 64)
+    say("[parity] full config1: running ds_process (graph)")
+    ds.ds_process(ctx.handle, ev, tr, vt, ds.DS_MODE_GRAPH)
+    torch.cuda.synchronize()
+    gt, gv = tr.to_numpy(), vt.to_numpy()
+    assert gt["flags"] == 0 and gv["flags"] == 0
+    rng = np.random.default_rng(0)
+    events = np.sort(rng.choice(b.n_events, 150, replace=False))
+    sub = b.subset(events)
+    ref = O.run_path(sub, G0, W, cap=64, n_threads=8)
+    idx = np.concatenate([np.arange(b.seed_off[e], b.seed_off[e + 1]) for e in events])
+    gsub = {k: (v[idx] if isinstance(v, np.ndarray) and v.shape[:1] == (b.n_seeds,) else v) for k, v in gt.items()}
+    tc = parity.compare_tracks(gsub, ref["tracks"])
+    mask = (ref["tracks"]["nhits"] > 0) & (gsub["nhits"] == ref["tracks"]["nhits"])
+    sc = parity.compare_scores(gsub["score"], ref["score"], mask)
+    cap = 64
+    gvs = dict(count=gv["count"][events], cap=cap, overflow=0, flags=0)
+    for k in ("i", "j", "x", "y", "z", "doca"):
+        gvs[k] = np.concatenate([gv[k][e * cap:(e + 1) * cap] for e in events])
+    ref["vertices"]["overflow"] = 0
+    parity.compare_vertices(gvs, ref["vertices"], G0["doca_max"], parity.excused_slot_set(sub, tc, sc))
+    say(f"[parity] full config1 sample: identical {tc['identical']}/{tc['n']}")
