@@ -1,0 +1,241 @@
+"""Benchmark of the Downstream tracking + vertexing hot path on one MI355X.
+
+One step = the whole path (hit staging and window search, candidate fits and
+selection, fused ghost-killer MLP, two-track vertexing) over one batch of
+synthetic events resident in HBM: the 10 000-event throughput batch (150
+seeds/event, 600 UT hits/layer) by default.  Steps rotate over four device
+copies of the batch so the 256 MB Infinity Cache cannot serve it.
+
+Prints one JSON line: whole-job events/s of the persistent, graph-replayed
+launch; the same batch on the plain per-event-launch path; the roofline of
+the dominant kernel (tracking) from its HIP-event-timed average duration; and
+the FP64 CPU oracle timed on the host's cores.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "events/s/GPU (tracking+vertexing) and p99 event latency at fixed rate vs plain"
+WORKLOADS = {
+    1: "throughput batch: 10000 events x 150 seeds (40% true), 600 UT hits/layer, FP32 SoA",
+    2: "uneven batch: 20000 events, pileup-scaled occupancy",
+    4: "stress batch: 5000 events x 300 seeds, 1200 UT hits/layer, all-pairs vertexing",
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in ("paper_2503_13092_amd/csrc/ds_kernels.h", "paper_2503_13092_amd/csrc/ds_api.hip"):
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def track_bytes_per_event(batch) -> float:
+    """Algorithmic bytes of the tracking launch: the event in once (seed
+    states 20 B/seed, hits 4 B/hit, offsets 20 B/event) and one 48 B track
+    record per seed out (x, y, tx, ty, q/p, chi2, score, 4 hit indices, nhits)."""
+    S, H, E = batch.n_seeds, batch.n_hits, batch.n_events
+    return (20.0 * S + 4.0 * H + 20.0 * E + 48.0 * S) / E
+
+
+def vertex_bytes(batch, kept: int, n_vertices: int) -> float:
+    """Algorithmic bytes of the vertex launch: nhits + score of every seed,
+    the state (x, y, tx, ty, q/p) and charge of kept tracks, 24 B per vertex
+    and a count per event."""
+    return 8.0 * batch.n_seeds + 24.0 * kept + 24.0 * n_vertices + 8.0 * batch.n_events
+
+
+def stored_traffic(kernel: str, src_hash: str):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    e = d.get(kernel)
+    if not e or e.get("source_hash") != src_hash:
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(batch, g, w):
+    """The oracle as it stands, on the host's cores, on a bounded sample."""
+    from oracle import pyoracle as O
+    try:
+        n_threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n_threads = os.cpu_count() or 1
+    n_threads = max(1, min(n_threads, 16))
+    # per-event cost from a short single-thread probe
+    probe = batch.subset(np.arange(min(50, batch.n_events)))
+    t0 = time.perf_counter()
+    O.run_path(probe, g, w, cap=64, n_threads=1)
+    per_event = (time.perf_counter() - t0) / probe.n_events
+    # about 20 s of CPU work (single-thread seconds), never more than the batch
+    n = int(min(batch.n_events, max(100, 20.0 / max(per_event, 1e-6))))
+    sample = batch.subset(np.arange(n))
+    t0 = time.perf_counter()
+    O.run_path(sample, g, w, cap=64, n_threads=n_threads)
+    dt = time.perf_counter() - t0
+    return dict(value=round(n / dt, 1), unit="events/s", cores=n_threads, kind="oracle",
+                sample=f"first {n} events of the batch, whole path (tracks, ghost-killer, vertices), "
+                       f"FP64, {n_threads} threads, {dt:.2f} s wall",
+                single_thread_events_per_s=round(1.0 / per_event, 1))
+
+
+def copy_ceiling_gbs(torch, nbytes=2 << 30, reps=10):
+    """Achievable HBM bandwidth of a plain device-to-device copy (read + write)."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    del a, b
+    return 2.0 * nbytes / dt / 1e9
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=1, choices=(1, 2, 4))
+    ap.add_argument("--copies", type=int, default=4, help="rotated device copies of the batch")
+    ap.add_argument("--plain-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-copy-ceiling", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for {args.gpus}); the path shards by "
+              f"independent events, see the design notes", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2503_13092_amd import ds, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    g = synth.default_geometry()
+    w = synth.mlp_weights()
+    t0 = time.perf_counter()
+    batch = synth.generate(args.config)
+    gen_s = time.perf_counter() - t0
+    E = batch.n_events
+    score_max = math.inf if args.config == 4 else g["ghost_threshold"]
+    cap = 1024 if args.config == 4 else 64
+
+    ctx = ds.Context(0, g, w)
+    copies = []
+    for _ in range(args.copies):
+        ev = ds.DeviceEvents(batch)
+        tr = ds.DeviceTracks(batch.n_seeds, with_cand=False)
+        vt = ds.DeviceVertices(E, cap)
+        copies.append((ev, tr, vt))
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    mode = ds.DS_MODE_GRAPH
+
+    def step(k, ev_pairs=None):
+        ev, tr, vt = copies[k % len(copies)]
+        if ev_pairs is not None:
+            ev_pairs[0].record(stream)
+        ds.ds_find_tracks(ctx.handle, ev, tr, mode, 1, stream)
+        if ev_pairs is not None:
+            ev_pairs[1].record(stream)
+        ds.ds_vertex(ctx.handle, ev, tr, score_max, vt, mode, stream)
+        if ev_pairs is not None:
+            ev_pairs[2].record(stream)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(k, events[k])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    trk_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in events]))
+    vtx_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in events]))
+    ms_per_step = dt * 1e3 / args.steps
+    value = E * args.steps / dt
+
+    # checks on the last copy written
+    ev, tr, vt = copies[(args.steps - 1) % len(copies)]
+    flags = int(tr.flags.item()) | int(vt.flags.item())
+    nh = tr.nhits.cpu().numpy()
+    sc = tr.score.cpu().numpy()
+    kept = int(np.sum((nh > 0) & (sc < score_max)))
+    n_vtx = int(vt.count.sum().item())
+
+    src_hash = kernel_source_hash()
+    bpe = track_bytes_per_event(batch)
+    achieved = bpe * E / (trk_ms * 1e-3) / 1e9
+    traffic = stored_traffic("k_track", src_hash)
+    roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 5), traffic=traffic,
+                    kernel="k_track (hit staging + search + fit + fused MLP)",
+                    kernel_ms=round(trk_ms, 4), algorithmic_bytes_per_launch=round(bpe * E))
+    vb = vertex_bytes(batch, kept, n_vtx)
+    vertex_info = dict(kernel_ms=round(vtx_ms, 4), algorithmic_bytes_per_launch=round(vb),
+                       achieved_GBs=round(vb / (vtx_ms * 1e-3) / 1e9, 2), kept_tracks=kept, vertices=n_vtx)
+
+    out = dict(metric=METRIC, value=round(value, 1), unit="events/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=round(ms_per_step, 4), higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="f64+f32", data="synthetic",
+               config=dict(workload=WORKLOADS[args.config], events_per_step=E, seeds=batch.n_seeds,
+                           hits=batch.n_hits, launch="persistent work-stealing, hipGraph replay",
+                           rotated_copies=args.copies),
+               roofline=roofline, vertex=vertex_info, flags=flags, kernel_source=src_hash)
+
+    if not args.no_plain:
+        pe = []
+        for k in range(args.plain_steps + 1):
+            ev, tr, vt = copies[k % len(copies)]
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ds.ds_find_tracks(ctx.handle, ev, tr, ds.DS_MODE_PER_EVENT, 1, stream)
+            ds.ds_vertex(ctx.handle, ev, tr, score_max, vt, ds.DS_MODE_PER_EVENT, stream)
+            torch.cuda.synchronize()
+            if k > 0:
+                pe.append(time.perf_counter() - t1)
+        pdt = float(np.mean(pe))
+        out["plain"] = dict(events_per_s=round(E / pdt, 1), ms_per_step=round(pdt * 1e3, 3),
+                            launches_per_step=2 * E, speedup_of_persistent=round(value / (E / pdt), 2))
+    if not args.no_copy_ceiling:
+        cc = copy_ceiling_gbs(torch)
+        out["roofline"]["copy_ceiling_GBs"] = round(cc, 1)
+        out["roofline"]["frac_of_copy_ceiling"] = round(achieved / cc, 5)
+    ctx.close()
+    del copies
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(batch, g, w)
+    else:
+        out["cpu_baseline"] = None
+    out["generate_s"] = round(gen_s, 2)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -252,11 +252,18 @@ __device__ inline void ghost_features(const DevGeom &G, float xf, float yf, floa
     f[16] = (float)(xm_trk - xm_seed);
 }
 
+// Read-only, wave-uniform parameters: loads through the constant address
+// space become scalar loads and the weights feed the FMAs as SGPR operands.
+typedef const __attribute__((address_space(4))) float cfloat;
+
 // 17 -> 32 ReLU -> 16 ReLU -> 1 sigmoid, float32 FMA; W is wave-uniform.
-__device__ inline float mlp_score(const float *__restrict__ W, const float f[NF])
+__device__ inline float mlp_score(const float *Wg, const float f[NF])
 {
-    const float *W1 = W, *b1 = W + NH1 * NF, *W2 = b1 + NH1, *b2 = W2 + NH2 * NH1, *W3 = b2 + NH2,
-                *b3 = W3 + NH2;
+    // opaque to the optimiser: keeps the scalar weight loads next to their
+    // uses instead of hoisting 1121 values out of the event loop into spills
+    asm volatile("" : "+s"(Wg));
+    cfloat *W = (cfloat *)(Wg);
+    cfloat *W1 = W, *b1 = W + NH1 * NF, *W2 = b1 + NH1, *b2 = W2 + NH2 * NH1, *W3 = b2 + NH2, *b3 = W3 + NH2;
     float h1[NH1];
 #pragma unroll
     for (int j = 0; j < NH1; ++j) {
@@ -430,23 +437,43 @@ __device__ inline void process_seed(const TrackArgs &a, const DevGeom &G, int i,
 
 // Stage one event's hits into LDS, bucket-sorted by (layer, bin) and sorted by
 // (u, index) inside each bucket.  E[b] = start of bucket b, E[4*nb] = count.
+// Hits are read once, HPT per lane per round with all loads in flight; the
+// bucket slot returned by the counting atomic is kept to place the hit after
+// the scan, so nothing is read twice.
 template <int BLOCK>
 __device__ inline bool stage_hits(const TrackArgs &a, int hb, const int hl[4], int nh, float *hu_s,
                                   uint16_t *hidx_s, int *E, int *s_bad, int *s_wsum)
 {
+    constexpr int HPT = 16;
     const int tid = threadIdx.x;
     const int NBT = 4 * a.nb;
     for (int k = tid; k <= NBT; k += BLOCK) E[k] = 0;
     if (tid == 0) *s_bad = 0;
     __syncthreads();
-    for (int k = tid; k < nh; k += BLOCK) {
-        const float u = a.hu[hb + k];
-        const int L = (k >= hl[1]) + (k >= hl[2]) + (k >= hl[3]);
-        if (!isfinite(u)) {
-            *s_bad = 1;
-            continue;
+    const int rounds = (nh + HPT * BLOCK - 1) / (HPT * BLOCK);
+    // events above HPT*BLOCK hits take several rounds; bucket counts accumulate across them
+    for (int r = 0; r < rounds; ++r) {
+        const int k0 = r * HPT * BLOCK + tid;
+        float u[HPT];
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) {
+            const int k = k0 + j * BLOCK;
+            u[j] = (k < nh) ? a.hu[hb + k] : 0.0f;
         }
-        atomicAdd(&E[L * a.nb + bin_of(u, a.u0, a.inv_bw, a.nb) + 1], 1);
+        bool bad = false;
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) {
+            const int k = k0 + j * BLOCK;
+            if (k < nh) {
+                if (!isfinite(u[j])) {
+                    bad = true;
+                } else {
+                    const int L = (k >= hl[1]) + (k >= hl[2]) + (k >= hl[3]);
+                    atomicAdd(&E[L * a.nb + bin_of(u[j], a.u0, a.inv_bw, a.nb) + 1], 1);
+                }
+            }
+        }
+        if (bad) *s_bad = 1;
     }
     __syncthreads();
     if (*s_bad) return false;
@@ -462,12 +489,24 @@ __device__ inline bool stage_hits(const TrackArgs &a, int hb, const int hl[4], i
         run += cnt;
     }
     __syncthreads();
-    for (int k = tid; k < nh; k += BLOCK) {
-        const float u = a.hu[hb + k];
-        const int L = (k >= hl[1]) + (k >= hl[2]) + (k >= hl[3]);
-        const int pos = atomicAdd(&E[L * a.nb + bin_of(u, a.u0, a.inv_bw, a.nb) + 1], 1);
-        hu_s[pos] = u;
-        hidx_s[pos] = (uint16_t)(k - hl[L]);
+    for (int r = 0; r < rounds; ++r) {
+        const int k0 = r * HPT * BLOCK + tid;
+        float u[HPT];
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) {
+            const int k = k0 + j * BLOCK;
+            u[j] = (k < nh) ? a.hu[hb + k] : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) {
+            const int k = k0 + j * BLOCK;
+            if (k < nh) {
+                const int L = (k >= hl[1]) + (k >= hl[2]) + (k >= hl[3]);
+                const int pos = atomicAdd(&E[L * a.nb + bin_of(u[j], a.u0, a.inv_bw, a.nb) + 1], 1);
+                hu_s[pos] = u[j];
+                hidx_s[pos] = (uint16_t)(k - hl[L]);
+            }
+        }
     }
     __syncthreads();
     // (u, index) order inside each bucket
