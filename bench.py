@@ -112,6 +112,28 @@ def copy_ceiling_gbs(torch, nbytes=2 << 30, reps=10):
     return 2.0 * nbytes / dt / 1e9
 
 
+def serving(g, w, seconds):
+    """Open-loop Poisson arrivals of uneven (pileup-scaled) events at fixed
+    rates; continuous batching over 3 in-flight slots vs the plain path (one
+    launch per event per step).  Latency = completion - scheduled arrival."""
+    from paper_2503_13092_amd import ds, serve, synth
+    pool = serve.EventPool(synth.generate(2, n_events=8000))
+    res = {}
+    for name, kw in (("batched", dict(n_slots=3, max_events=512, mode=ds.DS_MODE_PERSISTENT)),
+                     ("plain", dict(n_slots=1, max_events=1, mode=ds.DS_MODE_PER_EVENT))):
+        be = serve.GpuBackend(pool, g, w, **kw)
+        srv = serve.Server(be, pool)
+        srv.run(serve.poisson_arrivals(20000.0, 2000, seed=9))   # warm-up: contexts, caches
+        for rate in (20000.0, 50000.0, 100000.0):
+            n = int(rate * seconds)
+            _, st = srv.run(serve.poisson_arrivals(rate, n, seed=3), time_limit_s=4.0 * seconds + 2.0)
+            d = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.as_dict().items()}
+            d["offered"] = n
+            res.setdefault(str(int(rate)), {})[name] = d
+        be.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +145,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-copy-ceiling", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=1.5)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for {args.gpus}); the path shards by "
@@ -229,6 +253,8 @@ def main():
         out["roofline"]["frac_of_copy_ceiling"] = round(achieved / cc, 5)
     ctx.close()
     del copies
+    if not args.no_serve:
+        out["serving"] = serving(g, w, args.serve_seconds)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(batch, g, w)
     else:

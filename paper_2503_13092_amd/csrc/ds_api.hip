@@ -20,6 +20,7 @@ namespace {
 constexpr int MAX_STREAM_SLOTS = 64;
 constexpr int MAX_GRAPHS = 64;
 constexpr int VTX_PPT = 4;
+constexpr int ITEMS_PER_SEED = 4;
 constexpr size_t LDS_LIMIT = 160 * 1024 - 256;   // gfx950: 160 KiB per workgroup, minus static use
 constexpr float PRESCREEN_MARGIN = 0.1f;         // mm, see the float32 error bound of the pair prescreen
 
@@ -59,9 +60,19 @@ ds_status dev_err(hipError_t e) { return e == hipSuccess ? DS_OK : DS_E_DEVICE; 
 
 size_t round16(size_t v) { return (v + 15) & ~size_t(15); }
 
-size_t track_lds(int hcap, int nb) { return round16((size_t)hcap * 6) + (size_t)(4 * nb + 1) * 4; }
+size_t track_lds(int hcap, int nb, int block, int icap)
+{
+    size_t off = (size_t)hcap * 4;
+    off = round16(off + (size_t)hcap * 2);
+    off = round16(off + (size_t)(4 * nb + 1) * 4);
+    off += (size_t)block * sizeof(ds::SeedConst);
+    off += (size_t)block * 8;
+    off = round16(off + (size_t)block * 4);
+    off = round16(off + (size_t)icap * 4);
+    return off + (size_t)icap * 8;
+}
 
-size_t vertex_lds(int tcap, int block) { return (size_t)tcap * 24 + (size_t)block * VTX_PPT * 24; }
+size_t vertex_lds(int tcap, int block) { return ((size_t)tcap * 24 + (size_t)64 * VTX_PPT * 24) * (size_t)(block / 64); }
 
 int round_up(int v, int m) { return ((v + m - 1) / m) * m; }
 
@@ -182,7 +193,10 @@ ds_status plan_track(ds_ctx *c, const ds_events *ev, const ds_tracks *out, int f
 {
     const int nb = c->trk.bins;
     int hcap = round_up(std::max(ev->max_hits_per_event, 1), 64);
-    size_t lds = track_lds(hcap, nb);
+    const int block = c->trk.block;
+    // items per chunk: room for ITEMS_PER_SEED per seed; a chunk shrinks when its seeds need more
+    const int icap = std::max(block * ITEMS_PER_SEED, ds::MAX_L3);
+    size_t lds = track_lds(hcap, nb, block, icap);
     if (lds > LDS_LIMIT) return DS_E_CAPACITY;
     ds::TrackArgs &a = p->a;
     std::memset(&a, 0, sizeof(a));
@@ -218,10 +232,11 @@ ds_status plan_track(ds_ctx *c, const ds_events *ev, const ds_tracks *out, int f
     a.fuse_mlp = fuse ? 1 : 0;
     a.ev_single = -1;
     a.hcap = hcap;
+    a.icap = icap;
     a.nb = nb;
     a.u0 = (float)c->u_min;
     a.inv_bw = (float)((double)nb / (c->u_max - c->u_min));
-    p->block = c->trk.block;
+    p->block = block;
     p->grid = std::max(1, std::min(ev->n_events, c->n_cu * c->trk.wg_per_cu));
     p->lds = lds;
     return DS_OK;

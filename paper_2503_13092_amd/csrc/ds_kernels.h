@@ -68,6 +68,7 @@ struct TrackArgs {
     int fuse_mlp;
     int ev_single;       // >= 0: this launch processes only that event
     int hcap;            // LDS hit capacity of the launch
+    int icap;            // LDS capacity for (seed, UTbX hit) items of one seed chunk
     int nb;              // bins per layer
     float u0, inv_bw;    // bin = floor((u - u0) * inv_bw), clamped
 };
@@ -139,46 +140,36 @@ __device__ inline bool finite5(float a, float b, float c, float d, float e)
     return isfinite(a) && isfinite(b) && isfinite(c) && isfinite(d) && isfinite(e);
 }
 
-// Walks outward from the insertion point of `m` in a sorted (u, index) run,
-// returning positions in increasing (|u - m|, u, index) order while |u - m| <= W.
-struct Walker {
-    int lo, hi, left, right, run_cur, run_end;
+// Window order of hits: (|u - m|, u, index within the layer run), lexicographic.
+__device__ inline bool key_less(double da, float ua, int ia, double db, float ub, int ib)
+{
+    return da < db || (da == db && (ua < ub || (ua == ub && ia < ib)));
+}
+
+// LDS positions [p_lo, p_hi) of the buckets of `layer` covering [m - W, m + W]
+// (a superset of the window: membership is decided on |u - m| <= W).
+__device__ inline void bin_range(const int *E, int layer, int nb, float u0, float inv_bw, double m, double W,
+                                 int &p_lo, int &p_hi)
+{
+    const int b_lo = bin_of((float)(m - W - 1e-3), u0, inv_bw, nb);
+    const int b_hi = bin_of((float)(m + W + 1e-3), u0, inv_bw, nb);
+    p_lo = E[layer * nb + b_lo];
+    p_hi = E[layer * nb + b_hi + 1];
+}
+
+// Candidate key for the per-seed reduction: more hits first, then lower chi2
+// (non-negative double bits are monotone; the 8 lowest mantissa bits are
+// dropped), then lower candidate index.
+__device__ inline unsigned long long pack_key(int n, double chi2, int c)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(chi2);
+    return ((unsigned long long)(4 - n) << 63) | ((b >> 8) << 7) | (unsigned long long)c;
+}
+
+struct SeedConst {
+    double c[4];   // c_L = x_S(z_L) - y(z_L) tan(alpha_L)
+    double w2;     // refined window half-width
 };
-
-__device__ inline void walker_init(Walker &w, const float *hu, const int *E, int layer, int nb, float u0,
-                                   float inv_bw, double m)
-{
-    w.lo = E[layer * nb];
-    w.hi = E[(layer + 1) * nb];
-    int b = bin_of((float)m, u0, inv_bw, nb);
-    int p = E[layer * nb + b];
-    while (p > w.lo && (double)hu[p - 1] >= m) --p;
-    while (p < w.hi && (double)hu[p] < m) ++p;
-    w.left = p - 1;
-    w.right = p;
-    w.run_cur = 1;
-    w.run_end = 0;
-}
-
-__device__ inline int walker_next(Walker &w, const float *hu, double m, double W)
-{
-    if (w.run_cur <= w.run_end) return w.run_cur++;
-    double dl = (w.left >= w.lo) ? m - (double)hu[w.left] : INFINITY;
-    double dr = (w.right < w.hi) ? (double)hu[w.right] - m : INFINITY;
-    if (dl <= dr) {
-        if (!(dl <= W)) return -1;
-        // equal u on the left side: emit the run in index order
-        float ul = hu[w.left];
-        int q = w.left;
-        while (q - 1 >= w.lo && hu[q - 1] == ul) --q;
-        w.run_cur = q + 1;
-        w.run_end = w.left;
-        w.left = q - 1;
-        return q;
-    }
-    if (!(dr <= W)) return -1;
-    return w.right++;
-}
 
 // Least squares of residuals rho_L over a valid layer set (mask 11, 13, 14 or 15).
 __device__ inline void fit_residuals(const DevGeom &G, int mask, const double rho[4], double &alpha, double &beta,
@@ -264,22 +255,22 @@ __device__ inline float mlp_score(const float *Wg, const float f[NF])
     asm volatile("" : "+s"(Wg));
     cfloat *W = (cfloat *)(Wg);
     cfloat *W1 = W, *b1 = W + NH1 * NF, *W2 = b1 + NH1, *b2 = W2 + NH2 * NH1, *W3 = b2 + NH2, *b3 = W3 + NH2;
-    float h1[NH1];
+    // hidden layer 1 is consumed as it is produced: h2[k] accumulates
+    // W2[k][j] * h1[j] in increasing j, the same order as a full h1 vector
+    float h2[NH2];
+#pragma unroll
+    for (int k = 0; k < NH2; ++k) h2[k] = b2[k];
 #pragma unroll
     for (int j = 0; j < NH1; ++j) {
         float a = b1[j];
 #pragma unroll
         for (int k = 0; k < NF; ++k) a = fmaf(W1[j * NF + k], f[k], a);
-        h1[j] = fmaxf(a, 0.0f);
-    }
-    float h2[NH2];
+        const float h1j = fmaxf(a, 0.0f);
 #pragma unroll
-    for (int j = 0; j < NH2; ++j) {
-        float a = b2[j];
-#pragma unroll
-        for (int k = 0; k < NH1; ++k) a = fmaf(W2[j * NH1 + k], h1[k], a);
-        h2[j] = fmaxf(a, 0.0f);
+        for (int k = 0; k < NH2; ++k) h2[k] = fmaf(W2[k * NH1 + j], h1j, h2[k]);
     }
+#pragma unroll
+    for (int k = 0; k < NH2; ++k) h2[k] = fmaxf(h2[k], 0.0f);
     float z = b3[0];
 #pragma unroll
     for (int k = 0; k < NH2; ++k) z = fmaf(W3[k], h2[k], z);
@@ -305,141 +296,144 @@ __device__ inline void write_empty_track(const TrackArgs &a, int i)
     if (a.cand) a.cand[i] = -1;
 }
 
-// One seed, one lane: first window, refined windows, candidates, best.
-__device__ inline void process_seed(const TrackArgs &a, const DevGeom &G, int i, const float *hu_s,
-                                    const uint16_t *hidx_s, const int *E)
+// Seed constants of the residual frame and the first-window centre / width.
+__device__ inline bool seed_frame(const DevGeom &G, float fsx, float fsy, float fstx, float fsty, float fsq,
+                                  SeedConst &sc, double &m3, double &W1)
 {
-    const float fsx = a.sx[i], fsy = a.sy[i], fstx = a.stx[i], fsty = a.sty[i], fsq = a.sqop[i];
-    if (!finite5(fsx, fsy, fstx, fsty, fsq)) {
-        atomicOr(a.flags, F_NONFINITE);
-        write_empty_track(a, i);
-        return;
-    }
+    if (!finite5(fsx, fsy, fstx, fsty, fsq)) return false;
     const double sx = fsx, sy = fsy, stx = fstx, sty = fsty, sq = fsq;
-    double c[4];
 #pragma unroll
     for (int L = 0; L < 4; ++L) {
-        double dzs = G.zl[L] - G.zs;
-        double xs = fma(stx, dzs, sx);
-        double yl = fma(sty, dzs, sy);
-        c[L] = fma(-yl, G.tana[L], xs);
+        const double dzs = G.zl[L] - G.zs;
+        const double xs = fma(stx, dzs, sx);
+        const double yl = fma(sty, dzs, sy);
+        sc.c[L] = fma(-yl, G.tana[L], xs);
     }
     const double aq = fabs(sq);
-    const double W1 = fma(G.w1c1, aq, G.w1c0);
-    const double W2 = fma(G.w2c1, aq, G.w2c0);
-    const double m3 = c[3] + G.mk * sq * (G.zm - G.zl[3]);
+    W1 = fma(G.w1c1, aq, G.w1c0);
+    sc.w2 = fma(G.w2c1, aq, G.w2c0);
+    m3 = sc.c[3] + G.mk * sq * (G.zm - G.zl[3]);
+    return true;
+}
 
-    Walker w3;
-    walker_init(w3, hu_s, E, 3, a.nb, a.u0, a.inv_bw, m3);
-    int best_n = 0, best_c = -1;
-    double best_chi2 = 0.0, best_alpha = 0.0, best_beta = 0.0;
-    int bp0 = -1, bp1 = -1, bp2 = -1, bp3 = -1;
-
-    for (int r3 = 0; r3 < G.max_l3; ++r3) {
-        const int p3 = walker_next(w3, hu_s, m3, W1);
-        if (p3 < 0) break;
-        const double rho3 = (double)hu_s[p3] - c[3];
-        int A[3][MAX_CLOSEST];
-        int nA[3];
+// Best candidate through one UTbX hit (rank r3, LDS position p3): refined
+// windows in UTaX, UTaU, UTbV, the <= 4 candidates, their fits.
+__device__ inline void item_best(const DevGeom &G, const TrackArgs &a, const float *hu_s, const uint16_t *hidx_s,
+                                 const int *E, const SeedConst &sc, int r3, int p3, int &best_n, double &best_chi2,
+                                 int &best_c, int bp[4])
+{
+    const double rho3 = (double)hu_s[p3] - sc.c[3];
+    int A[3][MAX_CLOSEST];
+    int nA[3];
 #pragma unroll
-        for (int L = 0; L < 3; ++L) {
-            const double mL = fma(rho3, G.ffac[L], c[L]);
-            Walker wl;
-            walker_init(wl, hu_s, E, L, a.nb, a.u0, a.inv_bw, mL);
-            nA[L] = 0;
-            A[L][0] = -1;
-            A[L][1] = -1;
-#pragma unroll
-            for (int q = 0; q < MAX_CLOSEST; ++q) {
-                if (q < G.ncl[L] && nA[L] == q) {
-                    int p = walker_next(wl, hu_s, mL, W2);
-                    if (p >= 0) {
-                        A[L][q] = p;
-                        nA[L] = q + 1;
-                    }
-                }
+    for (int L = 0; L < 3; ++L) {
+        const double m = fma(rho3, G.ffac[L], sc.c[L]);
+        int lo, hi;
+        bin_range(E, L, a.nb, a.u0, a.inv_bw, m, sc.w2, lo, hi);
+        double d0 = INFINITY, d1 = INFINITY;
+        float u0k = 0.0f, u1k = 0.0f;
+        int i0k = 0, i1k = 0, p0k = -1, p1k = -1;
+        for (int p = lo; p < hi; ++p) {
+            const float u = hu_s[p];
+            const double d = fabs((double)u - m);
+            if (!(d <= sc.w2)) continue;
+            const int id = hidx_s[p];
+            if (key_less(d, u, id, d0, u0k, i0k)) {
+                d1 = d0; u1k = u0k; i1k = i0k; p1k = p0k;
+                d0 = d; u0k = u; i0k = id; p0k = p;
+            } else if (key_less(d, u, id, d1, u1k, i1k)) {
+                d1 = d; u1k = u; i1k = id; p1k = p;
             }
         }
-        double rho[4];
-        rho[3] = rho3;
+        A[L][0] = G.ncl[L] >= 1 ? p0k : -1;
+        A[L][1] = G.ncl[L] >= 2 ? p1k : -1;
+        nA[L] = (A[L][0] >= 0 ? 1 : 0) + (A[L][1] >= 0 ? 1 : 0);
+    }
+    best_n = 0;
+    best_chi2 = 0.0;
+    best_c = -1;
+    double rho[4];
+    rho[3] = rho3;
 #pragma unroll
-        for (int i0 = 0; i0 < MAX_CLOSEST; ++i0) {
-            if (i0 >= (nA[0] > 0 ? nA[0] : 1)) continue;
-            const int p0 = A[0][i0];
+    for (int i0 = 0; i0 < MAX_CLOSEST; ++i0) {
+        if (i0 >= (nA[0] > 0 ? nA[0] : 1)) continue;
+        const int p0 = A[0][i0];
 #pragma unroll
-            for (int i1 = 0; i1 < MAX_CLOSEST; ++i1) {
-                if (i1 >= (nA[1] > 0 ? nA[1] : 1)) continue;
-                const int p1 = A[1][i1];
+        for (int i1 = 0; i1 < MAX_CLOSEST; ++i1) {
+            if (i1 >= (nA[1] > 0 ? nA[1] : 1)) continue;
+            const int p1 = A[1][i1];
 #pragma unroll
-                for (int i2 = 0; i2 < MAX_CLOSEST; ++i2) {
-                    if (i2 >= (nA[2] > 0 ? nA[2] : 1)) continue;
-                    const int p2 = A[2][i2];
-                    const int mask = 8 | (p0 >= 0 ? 1 : 0) | (p1 >= 0 ? 2 : 0) | (p2 >= 0 ? 4 : 0);
-                    const int n = __popc(mask);
-                    if (n < 3 || (p0 < 0 && p1 < 0)) continue;
-                    rho[0] = p0 >= 0 ? (double)hu_s[p0] - c[0] : 0.0;
-                    rho[1] = p1 >= 0 ? (double)hu_s[p1] - c[1] : 0.0;
-                    rho[2] = p2 >= 0 ? (double)hu_s[p2] - c[2] : 0.0;
-                    double al, be, c2;
-                    fit_residuals(G, mask, rho, al, be, c2);
-                    if (n > best_n || (n == best_n && c2 < best_chi2)) {
-                        best_n = n;
-                        best_chi2 = c2;
-                        best_c = ((r3 * G.nw[0] + i0) * G.nw[1] + i1) * G.nw[2] + i2;
-                        best_alpha = al;
-                        best_beta = be;
-                        bp0 = p0;
-                        bp1 = p1;
-                        bp2 = p2;
-                        bp3 = p3;
-                    }
+            for (int i2 = 0; i2 < MAX_CLOSEST; ++i2) {
+                if (i2 >= (nA[2] > 0 ? nA[2] : 1)) continue;
+                const int p2 = A[2][i2];
+                const int mask = 8 | (p0 >= 0 ? 1 : 0) | (p1 >= 0 ? 2 : 0) | (p2 >= 0 ? 4 : 0);
+                const int n = __popc(mask);
+                if (n < 3 || (p0 < 0 && p1 < 0)) continue;
+                rho[0] = p0 >= 0 ? (double)hu_s[p0] - sc.c[0] : 0.0;
+                rho[1] = p1 >= 0 ? (double)hu_s[p1] - sc.c[1] : 0.0;
+                rho[2] = p2 >= 0 ? (double)hu_s[p2] - sc.c[2] : 0.0;
+                double al, be, c2;
+                fit_residuals(G, mask, rho, al, be, c2);
+                if (n > best_n || (n == best_n && c2 < best_chi2)) {
+                    best_n = n;
+                    best_chi2 = c2;
+                    best_c = ((r3 * G.nw[0] + i0) * G.nw[1] + i1) * G.nw[2] + i2;
+                    bp[0] = p0;
+                    bp[1] = p1;
+                    bp[2] = p2;
+                    bp[3] = p3;
                 }
             }
         }
     }
+}
 
-    if (best_n == 0) {
-        write_empty_track(a, i);
-        return;
-    }
-    const double xs_ref = fma(stx, G.zref - G.zs, sx);
-    const double ys_ref = fma(sty, G.zref - G.zs, sy);
-    const float xf = (float)(xs_ref + best_alpha);
-    const float txf = (float)(stx + best_beta);
-    const float yf = (float)ys_ref;
+// Write the selected candidate (LDS positions bp, -1 = none) as seed i's track.
+__device__ inline void write_track(const TrackArgs &a, const DevGeom &G, int i, const SeedConst &sc,
+                                   const float *hu_s, const uint16_t *hidx_s, const int bp[4], int c)
+{
+    const float fsx = a.sx[i], fsy = a.sy[i], fstx = a.stx[i], fsty = a.sty[i], fsq = a.sqop[i];
+    const int mask = (bp[0] >= 0 ? 1 : 0) | (bp[1] >= 0 ? 2 : 0) | (bp[2] >= 0 ? 4 : 0) | 8;
+    const int n = __popc(mask);
+    double rho[4];
+#pragma unroll
+    for (int L = 0; L < 4; ++L) rho[L] = bp[L] >= 0 ? (double)hu_s[bp[L]] - sc.c[L] : 0.0;
+    double al, be, c2;
+    fit_residuals(G, mask, rho, al, be, c2);
+    const double sx = fsx, sy = fsy, stx = fstx, sty = fsty;
+    const float xf = (float)(fma(stx, G.zref_seed, sx) + al);
+    const float txf = (float)(stx + be);
+    const float yf = (float)fma(sty, G.zref_seed, sy);
     const float tyf = fsty;
-    const float qf = (G.mk != 0.0) ? (float)(-best_beta / G.mk) : fsq;
-    const float c2f = (float)best_chi2;
+    const float qf = (G.mk != 0.0) ? (float)(-be / G.mk) : fsq;
+    const float c2f = (float)c2;
     a.x[i] = xf;
     a.y[i] = yf;
     a.tx[i] = txf;
     a.ty[i] = tyf;
     a.qop[i] = qf;
     a.chi2[i] = c2f;
-    a.h0[i] = bp0 >= 0 ? (int)hidx_s[bp0] : -1;
-    a.h1[i] = bp1 >= 0 ? (int)hidx_s[bp1] : -1;
-    a.h2[i] = bp2 >= 0 ? (int)hidx_s[bp2] : -1;
-    a.h3[i] = (int)hidx_s[bp3];
-    a.nhits[i] = best_n;
-    if (a.cand) a.cand[i] = best_c;
+    a.h0[i] = bp[0] >= 0 ? (int)hidx_s[bp[0]] : -1;
+    a.h1[i] = bp[1] >= 0 ? (int)hidx_s[bp[1]] : -1;
+    a.h2[i] = bp[2] >= 0 ? (int)hidx_s[bp[2]] : -1;
+    a.h3[i] = (int)hidx_s[bp[3]];
+    a.nhits[i] = n;
+    if (a.cand) a.cand[i] = c;
     if (a.fuse_mlp) {
         float hu4[4];
-        hu4[0] = bp0 >= 0 ? hu_s[bp0] : 0.0f;
-        hu4[1] = bp1 >= 0 ? hu_s[bp1] : 0.0f;
-        hu4[2] = bp2 >= 0 ? hu_s[bp2] : 0.0f;
-        hu4[3] = hu_s[bp3];
-        const int has = (bp0 >= 0 ? 1 : 0) | (bp1 >= 0 ? 2 : 0) | (bp2 >= 0 ? 4 : 0) | 8;
+#pragma unroll
+        for (int L = 0; L < 4; ++L) hu4[L] = bp[L] >= 0 ? hu_s[bp[L]] : 0.0f;
         float f[NF];
-        ghost_features(G, xf, yf, txf, tyf, qf, c2f, best_n, fsx, fsy, fstx, fsty, fsq, hu4, has, f);
+        ghost_features(G, xf, yf, txf, tyf, qf, c2f, n, fsx, fsy, fstx, fsty, fsq, hu4, mask, f);
         a.score[i] = mlp_score(a.W, f);
     }
 }
 
-// Stage one event's hits into LDS, bucket-sorted by (layer, bin) and sorted by
-// (u, index) inside each bucket.  E[b] = start of bucket b, E[4*nb] = count.
-// Hits are read once, HPT per lane per round with all loads in flight; the
-// bucket slot returned by the counting atomic is kept to place the hit after
-// the scan, so nothing is read twice.
+// Stage one event's hits into LDS, bucketed by (layer, bin); the order inside a
+// bucket is arbitrary (windows select by the full key).  Afterwards E[b] =
+// start of bucket b and E[4*nb] = count.  Hits are read HPT per lane per round
+// with all loads in flight; events of one round keep them in registers
+// between the counting and the placing pass.
 template <int BLOCK>
 __device__ inline bool stage_hits(const TrackArgs &a, int hb, const int hl[4], int nh, float *hu_s,
                                   uint16_t *hidx_s, int *E, int *s_bad, int *s_wsum)
@@ -451,10 +445,9 @@ __device__ inline bool stage_hits(const TrackArgs &a, int hb, const int hl[4], i
     if (tid == 0) *s_bad = 0;
     __syncthreads();
     const int rounds = (nh + HPT * BLOCK - 1) / (HPT * BLOCK);
-    // events above HPT*BLOCK hits take several rounds; bucket counts accumulate across them
+    float u[HPT];
     for (int r = 0; r < rounds; ++r) {
         const int k0 = r * HPT * BLOCK + tid;
-        float u[HPT];
 #pragma unroll
         for (int j = 0; j < HPT; ++j) {
             const int k = k0 + j * BLOCK;
@@ -477,25 +470,27 @@ __device__ inline bool stage_hits(const TrackArgs &a, int hb, const int hl[4], i
     }
     __syncthreads();
     if (*s_bad) return false;
-    // exclusive scan of the bucket counts held at E[1..NBT]
+    // exclusive scan of the bucket counts held at E[1..NBT]: E[b + 1] = start of bucket b
     const int per = NBT / BLOCK;
     int local = 0;
     for (int j = 0; j < per; ++j) local += E[1 + tid * per + j];
     int tot;
     int run = block_exclusive_scan<BLOCK>(local, s_wsum, &tot);
     for (int j = 0; j < per; ++j) {
-        int cnt = E[1 + tid * per + j];
+        const int cnt = E[1 + tid * per + j];
         E[1 + tid * per + j] = run;
         run += cnt;
     }
     __syncthreads();
+    // placing pass: E[b + 1] advances to the end of bucket b = start of bucket b + 1
     for (int r = 0; r < rounds; ++r) {
         const int k0 = r * HPT * BLOCK + tid;
-        float u[HPT];
+        if (rounds > 1) {
 #pragma unroll
-        for (int j = 0; j < HPT; ++j) {
-            const int k = k0 + j * BLOCK;
-            u[j] = (k < nh) ? a.hu[hb + k] : 0.0f;
+            for (int j = 0; j < HPT; ++j) {
+                const int k = k0 + j * BLOCK;
+                u[j] = (k < nh) ? a.hu[hb + k] : 0.0f;
+            }
         }
 #pragma unroll
         for (int j = 0; j < HPT; ++j) {
@@ -509,23 +504,6 @@ __device__ inline bool stage_hits(const TrackArgs &a, int hb, const int hl[4], i
         }
     }
     __syncthreads();
-    // (u, index) order inside each bucket
-    for (int b = tid; b < NBT; b += BLOCK) {
-        const int s = E[b], e = E[b + 1];
-        for (int i = s + 1; i < e; ++i) {
-            const float u = hu_s[i];
-            const uint16_t id = hidx_s[i];
-            int j = i - 1;
-            while (j >= s && (hu_s[j] > u || (hu_s[j] == u && hidx_s[j] > id))) {
-                hu_s[j + 1] = hu_s[j];
-                hidx_s[j + 1] = hidx_s[j];
-                --j;
-            }
-            hu_s[j + 1] = u;
-            hidx_s[j + 1] = id;
-        }
-    }
-    __syncthreads();
     return true;
 }
 
@@ -533,12 +511,26 @@ template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    float *hu_s = reinterpret_cast<float *>(smem);
-    uint16_t *hidx_s = reinterpret_cast<uint16_t *>(smem + (size_t)a.hcap * 4);
-    int *E = reinterpret_cast<int *>(smem + (size_t)a.hcap * 6 + ((a.hcap * 6) & 15 ? 16 - ((a.hcap * 6) & 15) : 0));
-    __shared__ int s_ev, s_bad;
+    size_t off = 0;
+    float *hu_s = reinterpret_cast<float *>(smem + off);
+    off += (size_t)a.hcap * 4;
+    uint16_t *hidx_s = reinterpret_cast<uint16_t *>(smem + off);
+    off = (off + (size_t)a.hcap * 2 + 15) & ~(size_t)15;
+    int *E = reinterpret_cast<int *>(smem + off);
+    off = (off + (size_t)(4 * a.nb + 1) * 4 + 15) & ~(size_t)15;
+    SeedConst *s_c = reinterpret_cast<SeedConst *>(smem + off);
+    off += (size_t)BLOCK * sizeof(SeedConst);
+    unsigned long long *s_key = reinterpret_cast<unsigned long long *>(smem + off);
+    off += (size_t)BLOCK * 8;
+    int *s_base = reinterpret_cast<int *>(smem + off);
+    off = (off + (size_t)BLOCK * 4 + 15) & ~(size_t)15;
+    uint32_t *it_desc = reinterpret_cast<uint32_t *>(smem + off);
+    off = (off + (size_t)a.icap * 4 + 15) & ~(size_t)15;
+    unsigned long long *it_hits = reinterpret_cast<unsigned long long *>(smem + off);
+    __shared__ int s_ev, s_bad, s_nacc, s_nitems;
     __shared__ int s_wsum[BLOCK / 64];
     const int tid = threadIdx.x;
+    const int per_r3 = G.nw[0] * G.nw[1] * G.nw[2];
 
     for (int iter = 0;; ++iter) {
         if (tid == 0) {
@@ -557,7 +549,7 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
         int ho[5];
 #pragma unroll
         for (int L = 0; L < 5; ++L) ho[L] = a.hit_off[4 * e + L];
-        bool seeds_ok = (0 <= s0) && (s0 <= s1) && (s1 <= a.n_seeds);
+        const bool seeds_ok = (0 <= s0) && (s0 <= s1) && (s1 <= a.n_seeds);
         bool hits_ok = (0 <= ho[0]) && (ho[4] <= a.n_hits);
 #pragma unroll
         for (int L = 0; L < 4; ++L) hits_ok = hits_ok && (ho[L] <= ho[L + 1]) && (ho[L + 1] - ho[L] <= 65535);
@@ -572,18 +564,106 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
             __syncthreads();
             continue;
         }
+        if (s1 == s0) {
+            __syncthreads();
+            continue;
+        }
         int hl[4];
 #pragma unroll
         for (int L = 0; L < 4; ++L) hl[L] = ho[L] - ho[0];
-        const bool staged = stage_hits<BLOCK>(a, ho[0], hl, nh, hu_s, hidx_s, E, &s_bad, s_wsum);
-        if (!staged) {
+        if (!stage_hits<BLOCK>(a, ho[0], hl, nh, hu_s, hidx_s, E, &s_bad, s_wsum)) {
             if (tid == 0) atomicOr(a.flags, F_NONFINITE);
             for (int i = s0 + tid; i < s1; i += BLOCK) write_empty_track(a, i);
             __syncthreads();
             continue;
         }
-        for (int i = s0 + tid; i < s1; i += BLOCK) process_seed(a, G, i, hu_s, hidx_s, E);
-        __syncthreads();
+
+        // seeds in chunks of at most BLOCK, shortened so that their items fit
+        for (int sc0 = s0; sc0 < s1;) {
+            if (tid == 0) {
+                s_nacc = min(BLOCK, s1 - sc0);
+                s_nitems = 0;
+            }
+            // phase A: lane per seed, first window in UTbX, ranks of its hits
+            const int i = sc0 + tid;
+            const bool have = i < s1;
+            SeedConst sc;
+            double m3 = 0.0, W1 = 0.0;
+            int n3 = 0, p_lo = 0, p_hi = 0;
+            if (have) {
+                if (seed_frame(G, a.sx[i], a.sy[i], a.stx[i], a.sty[i], a.sqop[i], sc, m3, W1)) {
+                    bin_range(E, 3, a.nb, a.u0, a.inv_bw, m3, W1, p_lo, p_hi);
+                    int n_in = 0;
+                    for (int p = p_lo; p < p_hi; ++p) n_in += (fabs((double)hu_s[p] - m3) <= W1) ? 1 : 0;
+                    n3 = min(n_in, G.max_l3);
+                } else {
+                    atomicOr(a.flags, F_NONFINITE);
+                }
+            }
+            int tot;
+            const int excl = block_exclusive_scan<BLOCK>(n3, s_wsum, &tot);
+            const bool acc = have && (excl + n3 <= a.icap);
+            if (have && !acc) atomicMin(&s_nacc, tid);
+            if (acc) {
+                s_c[tid] = sc;
+                s_key[tid] = ~0ull;
+                s_base[tid] = excl;
+                atomicMax(&s_nitems, excl + n3);
+                for (int p = p_lo; p < p_hi && n3 > 0; ++p) {
+                    const float up = hu_s[p];
+                    const double dp = fabs((double)up - m3);
+                    if (!(dp <= W1)) continue;
+                    const int ip = hidx_s[p];
+                    int rank = 0;
+                    for (int q = p_lo; q < p_hi; ++q) {
+                        const float uq = hu_s[q];
+                        const double dq = fabs((double)uq - m3);
+                        if (dq <= W1 && key_less(dq, uq, (int)hidx_s[q], dp, up, ip)) ++rank;
+                    }
+                    if (rank < n3) it_desc[excl + rank] = ((uint32_t)tid << 20) | ((uint32_t)rank << 16) | (uint32_t)p;
+                }
+            }
+            __syncthreads();
+            const int nacc = s_nacc, n_items = s_nitems;
+            // phase B: lane per (seed, UTbX hit) item
+            for (int it = tid; it < n_items; it += BLOCK) {
+                const uint32_t d = it_desc[it];
+                const int sl = (int)(d >> 20), r3 = (int)((d >> 16) & 15u), p3 = (int)(d & 0xffffu);
+                const SeedConst scs = s_c[sl];
+                int bn, bc, bp[4] = {-1, -1, -1, -1};
+                double bchi2;
+                item_best(G, a, hu_s, hidx_s, E, scs, r3, p3, bn, bchi2, bc, bp);
+                unsigned long long packed = ~0ull;
+                if (bn > 0) {
+                    atomicMin(&s_key[sl], pack_key(bn, bchi2, bc));
+                    packed = 0;
+#pragma unroll
+                    for (int L = 0; L < 4; ++L)
+                        packed |= (unsigned long long)(bp[L] >= 0 ? (unsigned)bp[L] : 0xffffu) << (16 * L);
+                }
+                it_hits[it] = packed;
+            }
+            __syncthreads();
+            // phase C: lane per seed, write the winner (and its ghost score)
+            if (tid < nacc) {
+                const unsigned long long key = s_key[tid];
+                if (key == ~0ull) {
+                    write_empty_track(a, i);
+                } else {
+                    const int c = (int)(key & 127ull);
+                    const unsigned long long hp = it_hits[s_base[tid] + c / per_r3];
+                    int bp[4];
+#pragma unroll
+                    for (int L = 0; L < 4; ++L) {
+                        const int v = (int)((hp >> (16 * L)) & 0xffffull);
+                        bp[L] = v == 0xffff ? -1 : v;
+                    }
+                    write_track(a, G, i, s_c[tid], hu_s, hidx_s, bp, c);
+                }
+            }
+            __syncthreads();
+            sc0 += nacc;
+        }
     }
     if (a.ev_single < 0 && tid == 0) {
         __threadfence();
@@ -707,68 +787,89 @@ __device__ inline void unrank_pair(int k, int n, int &pa, int &pb)
     pb = k - start(r) + r + 1;
 }
 
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline int wave_exclusive_scan(int v, int *total)
+{
+    const int lane = threadIdx.x & 63;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    *total = __shfl(x, 63, 64);
+    return x - v;
+}
+
+// Vertexing: every wavefront works on its own events (work-stealing), so a
+// small event costs no workgroup barrier.  Per event: kept tracks compacted in
+// slot order into the wave's LDS tile, pairs (a < b) visited in row-major
+// chunks of 64*PPT, a float32 straight-line prescreen, float64 Newton PCA of
+// the survivors, and an order-preserving compaction, so vertices come out in
+// (i, j) order.
 template <int BLOCK, int PPT>
 __global__ __launch_bounds__(BLOCK) void k_vertex(VertexArgs a, DevGeom G)
 {
-    constexpr int CH = BLOCK * PPT;
+    constexpr int CH = 64 * PPT;
     extern __shared__ __align__(16) unsigned char smem[];
-    float4 *st = reinterpret_cast<float4 *>(smem);                                  // x, y, tx, ty
-    float *sq = reinterpret_cast<float *>(smem + (size_t)a.tcap * 16);              // track q/p
-    int *sslot = reinterpret_cast<int *>(smem + (size_t)a.tcap * 20);               // slot << 1 | positive
-    int *qk = reinterpret_cast<int *>(smem + (size_t)a.tcap * 24);                  // survivor pairs a << 16 | b
-    float4 *qres = reinterpret_cast<float4 *>(smem + (size_t)a.tcap * 24 + CH * 4); // vx, vy, vz, doca
-    int *qpass = reinterpret_cast<int *>(smem + (size_t)a.tcap * 24 + CH * 20);
-    __shared__ int s_ev, s_n, s_out;
-    __shared__ int s_wsum[BLOCK / 64];
-    const int tid = threadIdx.x;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const size_t wave_bytes = (size_t)a.tcap * 24 + (size_t)CH * 24;
+    unsigned char *wb = smem + (size_t)wid * wave_bytes;
+    float4 *st = reinterpret_cast<float4 *>(wb);                                   // x, y, tx, ty
+    float *sq = reinterpret_cast<float *>(wb + (size_t)a.tcap * 16);               // track q/p
+    int *sslot = reinterpret_cast<int *>(wb + (size_t)a.tcap * 20);                // slot << 1 | positive
+    int *qk = reinterpret_cast<int *>(wb + (size_t)a.tcap * 24);                   // survivors a << 16 | b
+    float4 *qres = reinterpret_cast<float4 *>(wb + (size_t)a.tcap * 24 + CH * 4);  // vx, vy, vz, doca
+    int *qpass = reinterpret_cast<int *>(wb + (size_t)a.tcap * 24 + CH * 20);
     const bool curved = (G.fp != 0.0);
+    const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     for (int iter = 0;; ++iter) {
-        if (tid == 0) {
-            int e;
+        int e = 0;
+        if (lane == 0) {
             if (a.ev_single >= 0)
-                e = (iter == 0) ? a.ev_single : a.n_events;
+                e = (iter == 0 && wid == 0) ? a.ev_single : a.n_events;
             else
                 e = atomicAdd(&a.counter[0], 1);
-            s_ev = e;
-            s_n = 0;
-            s_out = 0;
         }
-        __syncthreads();
-        const int e = s_ev;
+        e = __shfl(e, 0, 64);
         if (e >= a.n_events) break;
         const int s0 = a.seed_off[e], s1 = a.seed_off[e + 1];
         const bool ok = (0 <= s0) && (s0 <= s1) && (s1 <= a.n_seeds);
         if (!ok || s1 - s0 > a.tcap || s1 - s0 > a.max_seeds) {
-            if (tid == 0) {
+            if (lane == 0) {
                 atomicOr(a.flags, ok ? F_CAPACITY : F_BAD_OFFSETS);
                 a.count[e] = 0;
             }
-            __syncthreads();
             continue;
         }
         // kept tracks, compacted in slot order
-        for (int base = s0; base < s1; base += BLOCK) {
-            const int i = base + tid;
-            int kept = 0;
+        int n = 0;
+        for (int base = s0; base < s1; base += 64) {
+            const int i = base + lane;
+            bool kept = false;
             if (i < s1) kept = (a.nhits[i] > 0) && (a.score[i] < a.score_max);
-            int tot;
-            const int pos = block_exclusive_scan<BLOCK>(kept, s_wsum, &tot);
+            const unsigned long long m = __ballot(kept);
             if (kept) {
-                const int k = s_n + pos;
+                const int k = n + __popcll(m & lt_mask);
                 st[k] = make_float4(a.x[i], a.y[i], a.tx[i], a.ty[i]);
                 sq[k] = a.qop[i];
                 sslot[k] = ((i - s0) << 1) | (a.sqop[i] > 0.0f ? 1 : 0);
             }
-            __syncthreads();
-            if (tid == 0) s_n += tot;
-            __syncthreads();
+            n += __popcll(m);
         }
-        const int n = s_n;
+        wave_sync();
         const int npairs = n * (n - 1) / 2;
+        int out_n = 0;
         for (int chunk = 0; chunk < npairs; chunk += CH) {
             // stage 1: float32 prescreen of PPT consecutive pairs per lane
-            const int k0 = chunk + tid * PPT;
+            const int k0 = chunk + lane * PPT;
             int pa = 0, pb = 0;
             if (k0 < npairs) unrank_pair(k0, n, pa, pb);
             int pairs[PPT];
@@ -797,39 +898,37 @@ __global__ __launch_bounds__(BLOCK) void k_vertex(VertexArgs a, DevGeom G)
                 }
             }
             int tot;
-            int pos = block_exclusive_scan<BLOCK>(__popc(bits), s_wsum, &tot);
+            int pos = wave_exclusive_scan(__popc(bits), &tot);
 #pragma unroll
             for (int r = 0; r < PPT; ++r)
                 if ((bits >> r) & 1) qk[pos++] = pairs[r];
-            __syncthreads();
+            wave_sync();
             // stage 2: float64 Newton refinement of the survivors
-            for (int q = tid; q < tot; q += BLOCK) {
+            for (int q = lane; q < tot; q += 64) {
                 const int ia = qk[q] >> 16, ib = qk[q] & 0xffff;
                 const float4 A = st[ia], B = st[ib];
                 const double g1 = -G.fp * (G.gc0 + G.gc1 * ((double)sq[ia] * 1e-3));
                 const double g2 = -G.fp * (G.gc0 + G.gc1 * ((double)sq[ib] * 1e-3));
                 double vx, vy, vz, dd;
                 const bool good = pca64(G, A.x, A.y, A.z, A.w, g1, B.x, B.y, B.z, B.w, g2, vx, vy, vz, dd);
-                const int pass = good && (dd < G.doca_max);
-                qpass[q] = pass;
+                qpass[q] = (good && (dd < G.doca_max)) ? 1 : 0;
                 qres[q] = make_float4((float)vx, (float)vy, (float)vz, (float)dd);
             }
-            __syncthreads();
-            // stage 3: ordered compaction of the passing pairs
+            wave_sync();
+            // stage 3: order-preserving compaction of the passing pairs
             int cnt = 0;
 #pragma unroll
             for (int r = 0; r < PPT; ++r) {
-                const int q = tid * PPT + r;
+                const int q = lane * PPT + r;
                 cnt += (q < tot) ? qpass[q] : 0;
             }
             int tot2;
-            int opos = block_exclusive_scan<BLOCK>(cnt, s_wsum, &tot2);
-            const int out0 = s_out;
+            int opos = wave_exclusive_scan(cnt, &tot2);
 #pragma unroll
             for (int r = 0; r < PPT; ++r) {
-                const int q = tid * PPT + r;
+                const int q = lane * PPT + r;
                 if (q < tot && qpass[q]) {
-                    const int m = out0 + opos++;
+                    const int m = out_n + opos++;
                     if (m < a.cap) {
                         const size_t o = (size_t)e * (size_t)a.cap + (size_t)m;
                         const int ia = qk[q] >> 16, ib = qk[q] & 0xffff;
@@ -843,21 +942,19 @@ __global__ __launch_bounds__(BLOCK) void k_vertex(VertexArgs a, DevGeom G)
                     }
                 }
             }
-            __syncthreads();
-            if (tid == 0) s_out += tot2;
-            __syncthreads();
+            out_n += tot2;
+            wave_sync();
         }
-        if (tid == 0) {
-            const int m = s_out;
-            a.count[e] = m < a.cap ? m : a.cap;
-            if (m > a.cap) atomicAdd(a.overflow, m - a.cap);
+        if (lane == 0) {
+            a.count[e] = out_n < a.cap ? out_n : a.cap;
+            if (out_n > a.cap) atomicAdd(a.overflow, out_n - a.cap);
         }
-        __syncthreads();
+        wave_sync();
     }
-    if (a.ev_single < 0 && tid == 0) {
+    if (a.ev_single < 0 && lane == 0) {
         __threadfence();
         const int done = atomicAdd(&a.counter[1], 1);
-        if (done == (int)gridDim.x - 1) {
+        if (done == (int)gridDim.x * (BLOCK / 64) - 1) {
             atomicExch(&a.counter[0], 0);
             atomicExch(&a.counter[1], 0);
             __threadfence();
