@@ -88,6 +88,8 @@ enum {
  *  doca_max            : a vertex is kept if its DOCA < doca_max.
  *  ghost_threshold     : a track is kept if its ghost score < threshold
  *                        ("Ghost Rejection"); used by ds_process.
+ *  clone_kill          : nonzero: ds_process kills clones (ds_kill_clones)
+ *                        between track finding and the ghost-killer.
  */
 typedef struct {
     double z_layer[4];
@@ -103,6 +105,7 @@ typedef struct {
     int32_t newton_iters;
     double doca_max;
     double ghost_threshold;
+    int32_t clone_kill;
 } ds_geometry;
 
 /*
@@ -184,6 +187,17 @@ ds_status ds_load_geometry(ds_ctx *ctx, const ds_geometry *g, const float *mlp_w
 ds_status ds_find_tracks(ds_ctx *ctx, const ds_events *ev, const ds_tracks *out, int mode, int fuse_mlp,
                          void *hip_stream);
 
+/*
+ * Clone killing ("Algorithm Design": among track pairs sharing more than two
+ * UT hits the lower-scored candidate is killed).  Within each event, a found
+ * track is killed when another found track shares more than two hits with it
+ * (same hit in the same layer) and is better: more hits, else lower chi2,
+ * else lower seed slot.  All pairs are judged on the tracks as found; a
+ * killed track is rewritten as "no track" (nhits 0, hits -1, state 0, score 0).
+ * Uses trk->flags for device-side offset/capacity errors.
+ */
+ds_status ds_kill_clones(ds_ctx *ctx, const ds_events *ev, const ds_tracks *trk, void *hip_stream);
+
 /* Ghost-killer scores of the tracks in `trk` (reads the stored track, the
  * seed and the chosen hits; writes trk->score). */
 ds_status ds_ghost_kill(ds_ctx *ctx, const ds_events *ev, const ds_tracks *trk, void *hip_stream);
@@ -197,8 +211,9 @@ ds_status ds_vertex(ds_ctx *ctx, const ds_events *ev, const ds_tracks *trk, floa
                     const ds_vertices *out, int mode, void *hip_stream);
 
 /* The whole step: ds_find_tracks (fused MLP) then ds_vertex with
- * score_max = ghost_threshold (or `score_max` if it is not NaN); in
- * DS_MODE_GRAPH both launches are one cached hipGraph. */
+ * score_max = ghost_threshold (or `score_max` if it is not NaN); with
+ * geometry clone_kill set: ds_find_tracks, ds_kill_clones, ds_ghost_kill,
+ * ds_vertex.  In DS_MODE_GRAPH all launches are one cached hipGraph. */
 ds_status ds_process(ds_ctx *ctx, const ds_events *ev, const ds_tracks *trk, float score_max,
                      const ds_vertices *out, int mode, void *hip_stream);
 

@@ -393,6 +393,40 @@ int orc_find_tracks(const orc_geom *g, int n_events, const int *seed_off, const 
     return 0;
 }
 
+/* ------------------------------------------------------- clone killing ---- */
+
+/* Clone killing ("Algorithm Design"): among found tracks of one event, a
+ * track is killed when another track shares more than two of its UT hits
+ * (same hit in the same layer) and has the better score.  Score order: more
+ * hits, then lower chi2, then lower seed slot.  Every pair is compared on
+ * the tracks as selected (a killed track still kills the tracks it beats).
+ * Writes killed[i] = 1/0; chi2 is the stored (float32) value. */
+int orc_kill_clones(int n_events, const int *seed_off, const int *nhits, const int *hits, const double *chi2,
+                    int *killed)
+{
+    for (int e = 0; e < n_events; ++e) {
+        int s0 = seed_off[e], s1 = seed_off[e + 1];
+        for (int i = s0; i < s1; ++i) {
+            killed[i] = 0;
+            if (nhits[i] <= 0) continue;
+            for (int j = s0; j < s1; ++j) {
+                if (j == i || nhits[j] <= 0) continue;
+                int shared = 0;
+                for (int L = 0; L < 4; ++L)
+                    if (hits[4 * i + L] >= 0 && hits[4 * i + L] == hits[4 * j + L]) ++shared;
+                if (shared <= 2) continue;
+                int j_better = nhits[j] > nhits[i] || (nhits[j] == nhits[i] && chi2[j] < chi2[i]) ||
+                               (nhits[j] == nhits[i] && chi2[j] == chi2[i] && j < i);
+                if (j_better) {
+                    killed[i] = 1;
+                    break;
+                }
+            }
+        }
+    }
+    return 0;
+}
+
 /* ---------------------------------------------------------------- O9 ---- */
 
 #define NF 17

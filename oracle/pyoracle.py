@@ -113,6 +113,29 @@ def find_tracks(batch, g: dict, n_threads: int = 1, float64_truth: bool = False)
     return out
 
 
+def kill_clones(seed_off, st: dict) -> np.ndarray:
+    """Clone-killing flags (1 = killed) of stored tracks."""
+    L = lib()
+    so_a, so_p = _i(seed_off)
+    nh_a, nh_p = _i(st["nhits"])
+    hh_a, hh_p = _i(np.asarray(st["hits"]).reshape(-1))
+    c2_a, c2_p = _d(st["chi2"])
+    killed = np.zeros(len(nh_a), np.int32)
+    L.orc_kill_clones(C.c_int(len(seed_off) - 1), so_p, nh_p, hh_p, c2_p, killed.ctypes.data_as(_ip))
+    return killed
+
+
+def apply_kills(st: dict, killed) -> dict:
+    """Killed tracks become 'no track' (as the library writes them)."""
+    out = {k: v.copy() for k, v in st.items()}
+    k = np.asarray(killed, bool)
+    for name in ("x", "y", "tx", "ty", "qop", "chi2"):
+        out[name][k] = 0
+    out["nhits"][k] = 0
+    out["hits"][k] = -1
+    return out
+
+
 def stored_tracks(tr: dict) -> dict:
     """The boundary's float32 track record made from oracle float64 tracks."""
     st = {k: tr[k].astype(np.float32) for k in ("x", "y", "tx", "ty", "qop", "chi2")}
@@ -187,11 +210,14 @@ def vertex_list(v: dict):
     return out
 
 
-def run_path(batch, g: dict, weights, score_max=None, cap: int = 1024, n_threads: int = 1) -> dict:
+def run_path(batch, g: dict, weights, score_max=None, cap: int = 1024, n_threads: int = 1,
+             clone_kill: bool = False) -> dict:
     """The whole path as the library runs it: tracks -> stored float32 ->
-    ghost-killer scores -> vertices of kept tracks."""
+    (clone killing) -> ghost-killer scores -> vertices of kept tracks."""
     tr = find_tracks(batch, g, n_threads=n_threads)
     st = stored_tracks(tr)
+    if clone_kill:
+        st = apply_kills(st, kill_clones(batch.seed_off, st))
     score = ghost_kill(batch, st, g, weights)
     if score_max is None:
         score_max = g["ghost_threshold"]

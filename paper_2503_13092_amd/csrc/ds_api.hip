@@ -21,6 +21,7 @@ constexpr int MAX_STREAM_SLOTS = 64;
 constexpr int MAX_GRAPHS = 64;
 constexpr int VTX_PPT = 4;
 constexpr int ITEMS_PER_SEED = 4;
+constexpr int CLONE_BLOCK = 256;
 constexpr size_t LDS_LIMIT = 160 * 1024 - 256;   // gfx950: 160 KiB per workgroup, minus static use
 constexpr float PRESCREEN_MARGIN = 0.1f;         // mm, see the float32 error bound of the pair prescreen
 
@@ -43,6 +44,7 @@ struct ds_ctx {
     ds::DevGeom G{};
     double u_min = -1000.0, u_max = 1000.0;
     double ghost_threshold = 0.5;
+    bool clone_kill = false;
     float *d_W = nullptr;
     int *d_counters = nullptr;  // [MAX_STREAM_SLOTS][4]
     std::map<void *, int> slots;
@@ -168,7 +170,8 @@ hipError_t set_kernel_attributes()
         reinterpret_cast<const void *>(&ds::k_vertex<64, VTX_PPT>),
         reinterpret_cast<const void *>(&ds::k_vertex<128, VTX_PPT>),
         reinterpret_cast<const void *>(&ds::k_vertex<256, VTX_PPT>),
-        reinterpret_cast<const void *>(&ds::k_vertex<512, VTX_PPT>)};
+        reinterpret_cast<const void *>(&ds::k_vertex<512, VTX_PPT>),
+        reinterpret_cast<const void *>(&ds::k_clone<CLONE_BLOCK>)};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_LIMIT);
         if (e != hipSuccess) return e;
@@ -281,6 +284,81 @@ ds_status plan_vertex(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, floa
     p->grid = std::max(1, std::min(ev->n_events, c->n_cu * c->vtx.wg_per_cu));
     p->lds = lds;
     return DS_OK;
+}
+
+ds::GhostArgs ghost_args(ds_ctx *c, const ds_events *ev, const ds_tracks *trk)
+{
+    ds::GhostArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.n_events = ev->n_events;
+    a.n_seeds = ev->n_seeds;
+    a.n_hits = ev->n_hits;
+    a.seed_off = ev->seed_off;
+    a.sx = ev->sx;
+    a.sy = ev->sy;
+    a.stx = ev->stx;
+    a.sty = ev->sty;
+    a.sqop = ev->sqop;
+    a.hit_off = ev->hit_off;
+    a.hu = ev->hu;
+    a.x = trk->x;
+    a.y = trk->y;
+    a.tx = trk->tx;
+    a.ty = trk->ty;
+    a.qop = trk->qop;
+    a.chi2 = trk->chi2;
+    a.h0 = trk->hit[0];
+    a.h1 = trk->hit[1];
+    a.h2 = trk->hit[2];
+    a.h3 = trk->hit[3];
+    a.nhits = trk->nhits;
+    a.score = trk->score;
+    a.flags = trk->flags;
+    a.W = c->d_W;
+    return a;
+}
+
+hipError_t launch_ghost(ds_ctx *c, const ds::GhostArgs &a, hipStream_t s)
+{
+    const int grid = std::max(1, std::min(a.n_events, c->n_cu * 8));
+    hipLaunchKernelGGL(ds::k_ghost<128>, dim3(grid), dim3(128), 0, s, a, c->G);
+    return hipGetLastError();
+}
+
+ds_status clone_args(const ds_events *ev, const ds_tracks *trk, ds::CloneArgs *a, size_t *lds)
+{
+    std::memset(a, 0, sizeof(*a));
+    const int tcap = round_up(std::max(ev->max_seeds_per_event, 1), 64);
+    *lds = (size_t)tcap * 16 * (CLONE_BLOCK / 64);
+    if (*lds > LDS_LIMIT) return DS_E_CAPACITY;
+    a->n_events = ev->n_events;
+    a->n_seeds = ev->n_seeds;
+    a->max_seeds = ev->max_seeds_per_event;
+    a->seed_off = ev->seed_off;
+    a->x = trk->x;
+    a->y = trk->y;
+    a->tx = trk->tx;
+    a->ty = trk->ty;
+    a->qop = trk->qop;
+    a->chi2 = trk->chi2;
+    a->score = trk->score;
+    a->h0 = trk->hit[0];
+    a->h1 = trk->hit[1];
+    a->h2 = trk->hit[2];
+    a->h3 = trk->hit[3];
+    a->nhits = trk->nhits;
+    a->cand = trk->cand;
+    a->flags = trk->flags;
+    a->tcap = tcap;
+    return DS_OK;
+}
+
+hipError_t launch_clone(ds_ctx *c, const ds::CloneArgs &a, size_t lds, hipStream_t s)
+{
+    const int waves = CLONE_BLOCK / 64;
+    const int grid = std::max(1, std::min((a.n_events + waves - 1) / waves, c->n_cu * 8));
+    hipLaunchKernelGGL(ds::k_clone<CLONE_BLOCK>, dim3(grid), dim3(CLONE_BLOCK), lds, s, a);
+    return hipGetLastError();
 }
 
 hipError_t run_track(ds_ctx *c, const TrackPlan &p, int mode, hipStream_t s)
@@ -480,6 +558,7 @@ ds_status ds_load_geometry(ds_ctx *c, const ds_geometry *g, const float *w, size
     c->u_min = g->u_min;
     c->u_max = g->u_max;
     c->ghost_threshold = g->ghost_threshold;
+    c->clone_kill = g->clone_kill != 0;
     // cached graphs hold the old geometry as kernel arguments
     for (auto &e : c->graphs) {
         (void)hipGraphExecDestroy(e.second.exec);
@@ -524,36 +603,25 @@ ds_status ds_ghost_kill(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, vo
     if (ev->n_events == 0) return DS_OK;
     std::lock_guard<std::mutex> lock(c->mu);
     if (hipSetDevice(c->device) != hipSuccess) return DS_E_DEVICE;
-    ds::GhostArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.n_events = ev->n_events;
-    a.n_seeds = ev->n_seeds;
-    a.n_hits = ev->n_hits;
-    a.seed_off = ev->seed_off;
-    a.sx = ev->sx;
-    a.sy = ev->sy;
-    a.stx = ev->stx;
-    a.sty = ev->sty;
-    a.sqop = ev->sqop;
-    a.hit_off = ev->hit_off;
-    a.hu = ev->hu;
-    a.x = trk->x;
-    a.y = trk->y;
-    a.tx = trk->tx;
-    a.ty = trk->ty;
-    a.qop = trk->qop;
-    a.chi2 = trk->chi2;
-    a.h0 = trk->hit[0];
-    a.h1 = trk->hit[1];
-    a.h2 = trk->hit[2];
-    a.h3 = trk->hit[3];
-    a.nhits = trk->nhits;
-    a.score = trk->score;
-    a.flags = trk->flags;
-    a.W = c->d_W;
-    const int grid = std::max(1, std::min(ev->n_events, c->n_cu * 8));
-    hipLaunchKernelGGL(ds::k_ghost<128>, dim3(grid), dim3(128), 0, reinterpret_cast<hipStream_t>(stream), a, c->G);
-    return dev_err(hipGetLastError());
+    return dev_err(launch_ghost(c, ghost_args(c, ev, trk), reinterpret_cast<hipStream_t>(stream)));
+}
+
+ds_status ds_kill_clones(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, void *stream)
+{
+    if (!c) return DS_E_ARG;
+    if (!c->loaded) return DS_E_STATE;
+    ds_status st = check_events(ev);
+    if (st != DS_OK) return st;
+    st = check_tracks(trk, ev->n_seeds, false);
+    if (st != DS_OK) return st;
+    if (ev->n_events == 0) return DS_OK;
+    std::lock_guard<std::mutex> lock(c->mu);
+    if (hipSetDevice(c->device) != hipSuccess) return DS_E_DEVICE;
+    ds::CloneArgs a;
+    size_t lds;
+    st = clone_args(ev, trk, &a, &lds);
+    if (st != DS_OK) return st;
+    return dev_err(launch_clone(c, a, lds, reinterpret_cast<hipStream_t>(stream)));
 }
 
 ds_status ds_vertex(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, float score_max, const ds_vertices *out,
@@ -606,17 +674,31 @@ ds_status ds_process(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, float
     int *counters;
     st = slot_for(c, stream, &counters);
     if (st != DS_OK) return st;
+    const bool ck = c->clone_kill;
     TrackPlan tp;
-    st = plan_track(c, ev, trk, 1, counters, &tp);
+    st = plan_track(c, ev, trk, ck ? 0 : 1, counters, &tp);
     if (st != DS_OK) return st;
     VertexPlan vp;
     st = plan_vertex(c, ev, trk, score_max, out, counters, &vp);
     if (st != DS_OK) return st;
-    std::string key = graph_key(2, &tp.a, sizeof(tp.a), tp.block, tp.grid, tp.lds);
+    ds::CloneArgs ca;
+    size_t clds = 0;
+    ds::GhostArgs ga = ghost_args(c, ev, trk);
+    if (ck) {
+        st = clone_args(ev, trk, &ca, &clds);
+        if (st != DS_OK) return st;
+    }
+    std::string key = graph_key(ck ? 4 : 2, &tp.a, sizeof(tp.a), tp.block, tp.grid, tp.lds);
     key += graph_key(3, &vp.a, sizeof(vp.a), vp.block, vp.grid, vp.lds);
     return run_maybe_graph(c, mode, key, s, [&](hipStream_t ss) {
         hipError_t e = run_track(c, tp, mode, ss);
         if (e != hipSuccess) return e;
+        if (ck) {
+            e = launch_clone(c, ca, clds, ss);
+            if (e != hipSuccess) return e;
+            e = launch_ghost(c, ga, ss);
+            if (e != hipSuccess) return e;
+        }
         return run_vertex(c, vp, mode, ss);
     });
 }

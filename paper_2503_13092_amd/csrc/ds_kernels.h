@@ -86,6 +86,14 @@ struct GhostArgs {
     const float *W;
 };
 
+struct CloneArgs {
+    int n_events, n_seeds, max_seeds;
+    const int *seed_off;
+    float *x, *y, *tx, *ty, *qop, *chi2, *score;
+    int *h0, *h1, *h2, *h3, *nhits, *cand, *flags;
+    int tcap;            // LDS capacity (seeds) per wavefront
+};
+
 struct VertexArgs {
     int n_events, n_seeds, max_seeds;
     const int *seed_off;
@@ -959,6 +967,82 @@ __global__ __launch_bounds__(BLOCK) void k_vertex(VertexArgs a, DevGeom G)
             atomicExch(&a.counter[1], 0);
             __threadfence();
         }
+    }
+}
+
+// Clone killing: one wavefront per event.  A found track is killed when
+// another found track of the event shares more than two UT hits with it and
+// has more hits, or as many and a lower chi2, or both equal and a lower slot.
+// Decisions are taken on LDS copies, so the kills of one event do not depend
+// on each other; a killed track is written as "no track".
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_clone(CloneArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    unsigned char *wb = smem + (size_t)wid * (size_t)a.tcap * 16;
+    unsigned long long *hp = reinterpret_cast<unsigned long long *>(wb);
+    int *nh = reinterpret_cast<int *>(wb + (size_t)a.tcap * 8);
+    float *c2 = reinterpret_cast<float *>(wb + (size_t)a.tcap * 12);
+    const int waves = (int)gridDim.x * (BLOCK / 64);
+    for (int e = (int)blockIdx.x * (BLOCK / 64) + wid; e < a.n_events; e += waves) {
+        const int s0 = a.seed_off[e], s1 = a.seed_off[e + 1];
+        const bool ok = (0 <= s0) && (s0 <= s1) && (s1 <= a.n_seeds);
+        if (!ok || s1 - s0 > a.tcap || s1 - s0 > a.max_seeds) {
+            if (lane == 0) atomicOr(a.flags, ok ? F_CAPACITY : F_BAD_OFFSETS);
+            continue;
+        }
+        const int n = s1 - s0;
+        for (int k = lane; k < n; k += 64) {
+            const int i = s0 + k;
+            const int h[4] = {a.h0[i], a.h1[i], a.h2[i], a.h3[i]};
+            unsigned long long p = 0;
+#pragma unroll
+            for (int L = 0; L < 4; ++L)
+                p |= (unsigned long long)(h[L] >= 0 ? ((unsigned)h[L] & 0xffffu) : 0xffffu) << (16 * L);
+            hp[k] = p;
+            nh[k] = a.nhits[i];
+            c2[k] = a.chi2[i];
+        }
+        wave_sync();
+        for (int k = lane; k < n; k += 64) {
+            const int nk = nh[k];
+            if (nk <= 0) continue;
+            const unsigned long long pk = hp[k];
+            const float ck = c2[k];
+            bool killed = false;
+            for (int j = 0; j < n && !killed; ++j) {
+                const int nj = nh[j];
+                if (j == k || nj <= 0) continue;
+                const unsigned long long pj = hp[j];
+                int shared = 0;
+#pragma unroll
+                for (int L = 0; L < 4; ++L) {
+                    const unsigned hk = (unsigned)(pk >> (16 * L)) & 0xffffu;
+                    shared += (hk != 0xffffu && hk == ((unsigned)(pj >> (16 * L)) & 0xffffu)) ? 1 : 0;
+                }
+                if (shared <= 2) continue;
+                const float cj = c2[j];
+                killed = nj > nk || (nj == nk && (cj < ck || (cj == ck && j < k)));
+            }
+            if (killed) {
+                const int i = s0 + k;
+                a.x[i] = 0.0f;
+                a.y[i] = 0.0f;
+                a.tx[i] = 0.0f;
+                a.ty[i] = 0.0f;
+                a.qop[i] = 0.0f;
+                a.chi2[i] = 0.0f;
+                if (a.score) a.score[i] = 0.0f;
+                a.h0[i] = -1;
+                a.h1[i] = -1;
+                a.h2[i] = -1;
+                a.h3[i] = -1;
+                a.nhits[i] = 0;
+                if (a.cand) a.cand[i] = -1;
+            }
+        }
+        wave_sync();
     }
 }
 

@@ -22,8 +22,8 @@ DS_MODE_PER_EVENT, DS_MODE_PERSISTENT, DS_MODE_GRAPH = 0, 1, 2
 DS_F_BAD_OFFSETS, DS_F_CAPACITY, DS_F_NONFINITE = 1, 2, 4
 N_WEIGHTS = 1121
 
-EXPORTED = ("ds_create", "ds_destroy", "ds_load_geometry", "ds_find_tracks", "ds_ghost_kill", "ds_vertex",
-            "ds_process", "ds_set_launch", "ds_get_launch", "ds_status_str")
+EXPORTED = ("ds_create", "ds_destroy", "ds_load_geometry", "ds_find_tracks", "ds_ghost_kill", "ds_kill_clones",
+            "ds_vertex", "ds_process", "ds_set_launch", "ds_get_launch", "ds_status_str")
 
 
 class DsGeometry(C.Structure):
@@ -41,6 +41,7 @@ class DsGeometry(C.Structure):
         ("newton_iters", C.c_int32),
         ("doca_max", C.c_double),
         ("ghost_threshold", C.c_double),
+        ("clone_kill", C.c_int32),
     ]
 
 
@@ -94,6 +95,7 @@ def library() -> C.CDLL:
         lib.ds_load_geometry.argtypes = [P, C.POINTER(DsGeometry), C.POINTER(C.c_float), C.c_size_t]
         lib.ds_find_tracks.argtypes = [P, C.POINTER(DsEvents), C.POINTER(DsTracks), C.c_int, C.c_int, P]
         lib.ds_ghost_kill.argtypes = [P, C.POINTER(DsEvents), C.POINTER(DsTracks), P]
+        lib.ds_kill_clones.argtypes = [P, C.POINTER(DsEvents), C.POINTER(DsTracks), P]
         lib.ds_vertex.argtypes = [P, C.POINTER(DsEvents), C.POINTER(DsTracks), C.c_float, C.POINTER(DsVertices),
                                   C.c_int, P]
         lib.ds_process.argtypes = [P, C.POINTER(DsEvents), C.POINTER(DsTracks), C.c_float, C.POINTER(DsVertices),
@@ -131,6 +133,7 @@ def geometry_struct(g: Dict) -> DsGeometry:
     s.max_l3 = int(g["max_l3"])
     s.n_closest[:] = [int(v) for v in g["n_closest"]]
     s.newton_iters = int(g["newton_iters"])
+    s.clone_kill = int(g.get("clone_kill", 0))
     return s
 
 
@@ -270,6 +273,11 @@ def ds_find_tracks(ctx, ev: DeviceEvents, trk: DeviceTracks, mode: int = DS_MODE
 def ds_ghost_kill(ctx, ev: DeviceEvents, trk: DeviceTracks, stream=None) -> None:
     _check(library().ds_ghost_kill(ctx, C.byref(ev.struct), C.byref(trk.struct), _stream_handle(stream)),
            "ds_ghost_kill")
+
+
+def ds_kill_clones(ctx, ev: DeviceEvents, trk: DeviceTracks, stream=None) -> None:
+    _check(library().ds_kill_clones(ctx, C.byref(ev.struct), C.byref(trk.struct), _stream_handle(stream)),
+           "ds_kill_clones")
 
 
 def ds_vertex(ctx, ev: DeviceEvents, trk: DeviceTracks, score_max: float, vtx: DeviceVertices,

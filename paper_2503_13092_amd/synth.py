@@ -79,6 +79,7 @@ def default_geometry(loose: bool = False) -> Dict:
         ghost_threshold=0.5,
         u_min=-(UT_XMAX + UT_YMAX * TAN5),
         u_max=(UT_XMAX + UT_YMAX * TAN5),
+        clone_kill=0,
     )
     if loose:
         g.update(w1_c0=100.0, w1_c1=0.0, w2_c0=10.0, w2_c1=0.0)

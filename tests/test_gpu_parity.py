@@ -308,3 +308,44 @@ def test_full_throughput_batch_sampled(ctx):
     ref["vertices"]["overflow"] = 0
     parity.compare_vertices(gvs, ref["vertices"], G0["doca_max"], parity.excused_slot_set(sub, tc, sc))
     say(f"[parity] full config1 sample: identical {tc['identical']}/{tc['n']}")
+
+
+def test_clone_killing_matches_oracle():
+    g = dict(G0, clone_kill=1)
+    c = ds.Context(0, g, W)
+    try:
+        for cfg, n in ((1, 200), (4, 40)):
+            b = synth.generate(cfg, n_events=n, seed=31)
+            ev = ds.DeviceEvents(b)
+            tr = ds.DeviceTracks(b.n_seeds)
+            ds.ds_find_tracks(c.handle, ev, tr, ds.DS_MODE_PERSISTENT, 0)
+            ds.ds_kill_clones(c.handle, ev, tr)
+            ds.ds_ghost_kill(c.handle, ev, tr)
+            torch.cuda.synchronize()
+            gt = tr.to_numpy()
+            ref_tr = O.find_tracks(b, g, n_threads=8)
+            st = O.stored_tracks(ref_tr)
+            killed = O.kill_clones(b.seed_off, st)
+            st2 = O.apply_kills(st, killed)
+            assert killed.sum() > 0
+            ref = dict(ref_tr)
+            for k in ("nhits", "hits"):
+                ref[k] = st2[k]
+            ref["cand"] = np.where(killed > 0, -1, ref_tr["cand"])
+            for k in ("x", "y", "tx", "ty", "qop", "chi2"):
+                ref[k] = np.where(killed > 0, 0.0, ref_tr[k])
+            tc = parity.compare_tracks(gt, ref)
+            score = O.ghost_kill(b, st2, g, W)
+            parity.compare_scores(gt["score"], score, st2["nhits"] > 0)
+            say(f"[parity] clone kill config{cfg}: killed {int(killed.sum())}, identical {tc['identical']}/{tc['n']}")
+            # the same through ds_process (graph) with clone_kill set
+            vt = ds.DeviceVertices(b.n_events, 1024)
+            tr2 = ds.DeviceTracks(b.n_seeds)
+            ds.ds_process(c.handle, ev, tr2, vt, ds.DS_MODE_GRAPH, score_max=math.inf)
+            torch.cuda.synchronize()
+            t2 = tr2.to_numpy()
+            for k in ("nhits", "hits", "score"):
+                assert np.array_equal(t2[k], gt[k]), k
+    finally:
+        torch.cuda.synchronize()
+        c.close()

@@ -47,7 +47,7 @@ int main(void) {
   printf("ds_geometry %zu\nds_events %zu\nds_tracks %zu\nds_vertices %zu\n", sizeof(ds_geometry),
          sizeof(ds_events), sizeof(ds_tracks), sizeof(ds_vertices));
   P(ds_geometry, max_l3) P(ds_geometry, n_closest) P(ds_geometry, gamma_c0) P(ds_geometry, newton_iters)
-  P(ds_geometry, doca_max) P(ds_geometry, ghost_threshold) P(ds_events, seed_off) P(ds_events, hu)
+  P(ds_geometry, doca_max) P(ds_geometry, ghost_threshold) P(ds_geometry, clone_kill) P(ds_events, seed_off) P(ds_events, hu)
   P(ds_tracks, hit) P(ds_tracks, nhits) P(ds_tracks, flags) P(ds_vertices, count) P(ds_vertices, flags)
   return 0;
 }

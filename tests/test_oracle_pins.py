@@ -470,3 +470,47 @@ def test_empty_and_degenerate_events():
     assert list(tr["nhits"]) == [0, 0, 0]
     b0 = synth.batch_from_lists([], dtype=np.float64)
     assert O.find_tracks(b0, g)["nhits"].size == 0
+
+
+# ------------------------------------------------------- clone killing -----
+
+def _st(nhits, hits, chi2):
+    return dict(nhits=np.array(nhits, np.int32), hits=np.array(hits, np.int32), chi2=np.array(chi2, np.float32))
+
+
+def test_clone_killing_rules():
+    # slots 0,1 share 3 hits: the higher chi2 dies; 2 shares only 2 hits with 0; 3 shares 3 with 0 but has more hits
+    st = _st([4, 4, 4, 4, 3], [[1, 2, 3, 4], [1, 2, 3, 9], [1, 2, 7, 8], [5, 2, 3, 4], [-1, 2, 3, 4]],
+             [1.0, 2.0, 0.5, 3.0, 0.1])
+    k = O.kill_clones(np.array([0, 5], np.int32), st)
+    # 0 vs 1: shared 3, 0 better -> 1 killed; 0 vs 3: shared 3 (2,3,4), 0 better -> 3 killed;
+    # 4 (3 hits) shares 3 with 0 and 3 -> killed; 2 shares 2 with 0 -> alive; 0 alive
+    assert list(k) == [0, 1, 0, 1, 1]
+
+
+def test_clone_killing_ties_and_events():
+    # equal hits and chi2: the lower slot wins; tracks in different events never interact
+    st = _st([4, 4, 4], [[1, 2, 3, 4], [1, 2, 3, 4], [1, 2, 3, 4]], [2.0, 2.0, 2.0])
+    assert list(O.kill_clones(np.array([0, 2, 3], np.int32), st)) == [0, 1, 0]
+    # a track beaten by a killed track is still killed (pairwise rule)
+    st = _st([4, 4, 4], [[1, 2, 3, 4], [1, 2, 3, 9], [5, 2, 3, 9]], [1.0, 2.0, 3.0])
+    assert list(O.kill_clones(np.array([0, 3], np.int32), st)) == [0, 1, 1]
+    # no track (nhits 0) neither kills nor is killed
+    st = _st([0, 4], [[1, 2, 3, 4], [1, 2, 3, 4]], [0.0, 5.0])
+    assert list(O.kill_clones(np.array([0, 2], np.int32), st)) == [0, 0]
+
+
+def test_clone_killing_on_generated_events_removes_few():
+    b = synth.generate(1, n_events=40, seed=12)
+    st = O.stored_tracks(O.find_tracks(b, G))
+    k = O.kill_clones(b.seed_off, st)
+    found = st["nhits"] > 0
+    frac = k.sum() / max(found.sum(), 1)
+    assert 0.0 <= frac < 0.05
+    # a killed track always shares > 2 hits with a surviving or better track of its event
+    for i in np.nonzero(k)[0]:
+        e = np.searchsorted(b.seed_off, i, side="right") - 1
+        js = range(b.seed_off[e], b.seed_off[e + 1])
+        assert any(j != i and st["nhits"][j] > 0 and
+                   sum(st["hits"][i, L] >= 0 and st["hits"][i, L] == st["hits"][j, L] for L in range(4)) > 2
+                   for j in js)
