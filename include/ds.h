@@ -165,6 +165,22 @@ typedef struct {
     int32_t *flags;
 } ds_vertices;
 
+/*
+ * Every enumerated candidate, scored: the ghost-killer is trained on all
+ * candidates found with wide windows and clone killing off ("Ghost-Killer
+ * Neural Network").  Row r = seed * ds_candidate_slots() + candidate index
+ * holds that candidate as if it were the selected track (float32 state at
+ * z_ref, chi2, hits, ghost score); rows of candidates that do not exist or
+ * are invalid have nhits = 0.  capacity >= n_seeds * ds_candidate_slots().
+ */
+typedef struct {
+    int32_t capacity;
+    int32_t *seed, *cand, *nhits;
+    int32_t *hit[4];
+    float *x, *y, *tx, *ty, *qop, *chi2, *score;
+    int32_t *flags;
+} ds_candidates;
+
 /* Create a context on HIP device `device`.  *ctx is set on DS_OK. */
 ds_status ds_create(ds_ctx **ctx, int device);
 
@@ -197,6 +213,12 @@ ds_status ds_find_tracks(ds_ctx *ctx, const ds_events *ev, const ds_tracks *out,
  * Uses trk->flags for device-side offset/capacity errors.
  */
 ds_status ds_kill_clones(ds_ctx *ctx, const ds_events *ev, const ds_tracks *trk, void *hip_stream);
+
+/* Candidate rows per seed for the loaded geometry: max_l3 * prod(max(n_closest, 1)); 0 before loading. */
+int ds_candidate_slots(ds_ctx *ctx);
+
+/* Score every valid candidate of every seed (see ds_candidates). */
+ds_status ds_score_candidates(ds_ctx *ctx, const ds_events *ev, const ds_candidates *out, void *hip_stream);
 
 /* Ghost-killer scores of the tracks in `trk` (reads the stored track, the
  * seed and the chosen hits; writes trk->score). */

@@ -429,6 +429,9 @@ int orc_kill_clones(int n_events, const int *seed_off, const int *nhits, const i
 
 /* ---------------------------------------------------------------- O9 ---- */
 
+void orc_features(const orc_geom *g, const double *trk, int nh, const double *s, const double *hit_u, double *f);
+double orc_mlp(const double *w, const double *f);
+
 #define NF 17
 #define NH1 32
 #define NH2 16
@@ -517,6 +520,75 @@ int orc_ghost_kill(const orc_geom *g, int n_events, const int *seed_off, const d
         }
     }
     return 0;
+}
+
+/* ------------------------------------------------ every candidate scored -- */
+
+/* Every valid candidate of every seed as a track of its own ("Ghost-Killer
+ * Neural Network": the network is trained on the candidates found with wide
+ * windows and clone killing off): the candidate's fit stored as float32 like a
+ * selected track, its 17 features and its score.  Rows are written in (seed,
+ * candidate index) order; returns the number of rows (at most max_rows). */
+int orc_score_candidates(const orc_geom *g, int n_events, const int *seed_off, const double *sx, const double *sy,
+                         const double *stx, const double *sty, const double *sqop, const int *hit_off,
+                         const double *hu, const double *w, int max_rows, int *row_seed, int *row_cand,
+                         int *row_hits, int *row_nhits, double *row_state /* [6]: x y tx ty qop chi2 (f32) */,
+                         double *row_score)
+{
+    int per3 = 1;
+    for (int L = 0; L < 3; ++L) per3 *= (g->n_closest[L] > 0 ? g->n_closest[L] : 1);
+    int maxc = (g->max_l3 > 0 ? g->max_l3 : 1) * per3;
+    cand_t *cands = (cand_t *)malloc(sizeof(cand_t) * (size_t)maxc);
+    int rows = 0;
+    for (int e = 0; e < n_events; ++e) {
+        const double *u[4];
+        int n[4], tot = 0;
+        for (int L = 0; L < 4; ++L) {
+            u[L] = hu + hit_off[4 * e + L];
+            n[L] = hit_off[4 * e + L + 1] - hit_off[4 * e + L];
+            tot += n[L];
+        }
+        if (!all_finite(hu + hit_off[4 * e], tot)) continue;
+        win_hit *scratch = (win_hit *)malloc(sizeof(win_hit) * (size_t)(tot + 1));
+        for (int i = seed_off[e]; i < seed_off[e + 1]; ++i) {
+            double s[5] = {sx[i], sy[i], stx[i], sty[i], sqop[i]};
+            if (!all_finite(s, 5)) continue;
+            fragility fr = {INFINITY, INFINITY};
+            int total = 0;
+            int m = enumerate_candidates(g, s, u, n, cands, maxc, &total, &fr, scratch);
+            for (int k = 0; k < m; ++k) {
+                const cand_t *cd = &cands[k];
+                if (!cd->valid) continue;
+                if (rows < max_rows) {
+                    double mk = g->polarity * g->kick;
+                    /* the stored float32 record, then features of it */
+                    double trk[6];
+                    trk[0] = (float)cd->a;
+                    trk[1] = (float)(s[1] + s[3] * (g->z_ref - g->z_seed));
+                    trk[2] = (float)cd->b;
+                    trk[3] = (float)s[3];
+                    trk[4] = (float)((mk != 0.0) ? (s[2] - cd->b) / mk : s[4]);
+                    trk[5] = (float)cd->chi2;
+                    double sf[5];
+                    for (int q = 0; q < 5; ++q) sf[q] = (float)s[q];
+                    double hu4[4];
+                    for (int L = 0; L < 4; ++L) hu4[L] = cd->hit[L] >= 0 ? u[L][cd->hit[L]] : NAN;
+                    double f[NF];
+                    orc_features(g, trk, cd->nhits, sf, hu4, f);
+                    row_seed[rows] = i;
+                    row_cand[rows] = cd->c;
+                    for (int L = 0; L < 4; ++L) row_hits[4 * rows + L] = cd->hit[L];
+                    row_nhits[rows] = cd->nhits;
+                    for (int q = 0; q < 6; ++q) row_state[6 * rows + q] = trk[q];
+                    row_score[rows] = orc_mlp(w, f);
+                }
+                ++rows;
+            }
+        }
+        free(scratch);
+    }
+    free(cands);
+    return rows < max_rows ? rows : max_rows;
 }
 
 /* --------------------------------------------------------------- O10 ---- */

@@ -136,6 +136,34 @@ def apply_kills(st: dict, killed) -> dict:
     return out
 
 
+def score_candidates(batch, g: dict, weights, max_rows: int = 10 ** 7) -> dict:
+    """Every valid candidate of every seed as a stored track with its score."""
+    L = lib()
+    keep = []
+
+    def d(a):
+        arr, p = _d(a)
+        keep.append(arr)
+        return p
+
+    so_a, so_p = _i(batch.seed_off)
+    ho_a, ho_p = _i(batch.hit_off)
+    n = max_rows
+    seed = np.zeros(n, np.int32)
+    cand = np.zeros(n, np.int32)
+    hits = np.zeros((n, 4), np.int32)
+    nh = np.zeros(n, np.int32)
+    state = np.zeros((n, 6))
+    score = np.zeros(n)
+    geom = make_geom(g)
+    m = L.orc_score_candidates(C.byref(geom), C.c_int(batch.n_events), so_p, d(batch.sx), d(batch.sy),
+                               d(batch.stx), d(batch.sty), d(batch.sqop), ho_p, d(batch.hu), d(np.asarray(weights)),
+                               C.c_int(n), seed.ctypes.data_as(_ip), cand.ctypes.data_as(_ip),
+                               hits.ctypes.data_as(_ip), nh.ctypes.data_as(_ip), state.ctypes.data_as(_dp),
+                               score.ctypes.data_as(_dp))
+    return dict(seed=seed[:m], cand=cand[:m], hits=hits[:m], nhits=nh[:m], state=state[:m], score=score[:m])
+
+
 def stored_tracks(tr: dict) -> dict:
     """The boundary's float32 track record made from oracle float64 tracks."""
     st = {k: tr[k].astype(np.float32) for k in ("x", "y", "tx", "ty", "qop", "chi2")}

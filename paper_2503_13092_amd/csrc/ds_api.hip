@@ -128,7 +128,10 @@ void append_bytes(std::string &key, const K &v)
 template <int B>
 hipError_t launch_track_b(const ds::TrackArgs &a, const ds::DevGeom &G, int grid, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL(ds::k_track<B>, dim3(grid), dim3(B), lds, s, a, G);
+    if (a.cmax > 0)
+        hipLaunchKernelGGL((ds::k_track<B, true>), dim3(grid), dim3(B), lds, s, a, G);
+    else
+        hipLaunchKernelGGL((ds::k_track<B, false>), dim3(grid), dim3(B), lds, s, a, G);
     return hipGetLastError();
 }
 
@@ -165,8 +168,14 @@ hipError_t launch_vertex(int block, const ds::VertexArgs &a, const ds::DevGeom &
 hipError_t set_kernel_attributes()
 {
     const void *fns[] = {
-        reinterpret_cast<const void *>(&ds::k_track<64>), reinterpret_cast<const void *>(&ds::k_track<128>),
-        reinterpret_cast<const void *>(&ds::k_track<256>), reinterpret_cast<const void *>(&ds::k_track<512>),
+        reinterpret_cast<const void *>(&ds::k_track<64, false>),
+        reinterpret_cast<const void *>(&ds::k_track<128, false>),
+        reinterpret_cast<const void *>(&ds::k_track<256, false>),
+        reinterpret_cast<const void *>(&ds::k_track<512, false>),
+        reinterpret_cast<const void *>(&ds::k_track<64, true>),
+        reinterpret_cast<const void *>(&ds::k_track<128, true>),
+        reinterpret_cast<const void *>(&ds::k_track<256, true>),
+        reinterpret_cast<const void *>(&ds::k_track<512, true>),
         reinterpret_cast<const void *>(&ds::k_vertex<64, VTX_PPT>),
         reinterpret_cast<const void *>(&ds::k_vertex<128, VTX_PPT>),
         reinterpret_cast<const void *>(&ds::k_vertex<256, VTX_PPT>),
@@ -622,6 +631,66 @@ ds_status ds_kill_clones(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, v
     st = clone_args(ev, trk, &a, &lds);
     if (st != DS_OK) return st;
     return dev_err(launch_clone(c, a, lds, reinterpret_cast<hipStream_t>(stream)));
+}
+
+int ds_candidate_slots(ds_ctx *c)
+{
+    if (!c || !c->loaded) return 0;
+    return c->G.max_l3 * c->G.nw[0] * c->G.nw[1] * c->G.nw[2];
+}
+
+ds_status ds_score_candidates(ds_ctx *c, const ds_events *ev, const ds_candidates *out, void *stream)
+{
+    if (!c) return DS_E_ARG;
+    if (!c->loaded) return DS_E_STATE;
+    ds_status st = check_events(ev);
+    if (st != DS_OK) return st;
+    if (!out || !out->flags || out->capacity < 0) return DS_E_ARG;
+    if (ev->n_events == 0) return DS_OK;
+    const int cmax = c->G.max_l3 * c->G.nw[0] * c->G.nw[1] * c->G.nw[2];
+    if (cmax <= 0) return DS_OK;
+    if ((long long)out->capacity < (long long)ev->n_seeds * cmax) return DS_E_CAPACITY;
+    if (ev->n_seeds > 0) {
+        if (!out->seed || !out->cand || !out->nhits || !out->x || !out->y || !out->tx || !out->ty || !out->qop ||
+            !out->chi2 || !out->score)
+            return DS_E_ARG;
+        for (int L = 0; L < 4; ++L)
+            if (!out->hit[L]) return DS_E_ARG;
+    }
+    std::lock_guard<std::mutex> lock(c->mu);
+    if (hipSetDevice(c->device) != hipSuccess) return DS_E_DEVICE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int *counters;
+    st = slot_for(c, stream, &counters);
+    if (st != DS_OK) return st;
+    ds_tracks none;
+    std::memset(&none, 0, sizeof(none));
+    none.flags = out->flags;
+    TrackPlan p;
+    st = plan_track(c, ev, &none, 0, counters, &p);
+    if (st != DS_OK) return st;
+    p.a.cmax = cmax;
+    p.a.r_seed = out->seed;
+    p.a.r_cand = out->cand;
+    p.a.r_nhits = out->nhits;
+    p.a.r_h0 = out->hit[0];
+    p.a.r_h1 = out->hit[1];
+    p.a.r_h2 = out->hit[2];
+    p.a.r_h3 = out->hit[3];
+    p.a.r_x = out->x;
+    p.a.r_y = out->y;
+    p.a.r_tx = out->tx;
+    p.a.r_ty = out->ty;
+    p.a.r_qop = out->qop;
+    p.a.r_chi2 = out->chi2;
+    p.a.r_score = out->score;
+    const long long rows = (long long)ev->n_seeds * cmax;
+    if (rows > 0) {
+        const int grid = (int)std::min<long long>((rows + 255) / 256, (long long)c->n_cu * 16);
+        hipLaunchKernelGGL(ds::k_clear_rows, dim3(grid), dim3(256), 0, s, out->nhits, rows);
+        if (hipGetLastError() != hipSuccess) return DS_E_DEVICE;
+    }
+    return dev_err(run_track(c, p, DS_MODE_PERSISTENT, s));
 }
 
 ds_status ds_vertex(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, float score_max, const ds_vertices *out,

@@ -69,6 +69,10 @@ struct TrackArgs {
     int ev_single;       // >= 0: this launch processes only that event
     int hcap;            // LDS hit capacity of the launch
     int icap;            // LDS capacity for (seed, UTbX hit) items of one seed chunk
+    // candidate-scoring mode: rows [n_seeds * cmax], row = seed * cmax + candidate index
+    int cmax;
+    int *r_seed, *r_cand, *r_nhits, *r_h0, *r_h1, *r_h2, *r_h3;
+    float *r_x, *r_y, *r_tx, *r_ty, *r_qop, *r_chi2, *r_score;
     int nb;              // bins per layer
     float u0, inv_bw;    // bin = floor((u - u0) * inv_bw), clamped
 };
@@ -289,6 +293,7 @@ __device__ inline float mlp_score(const float *Wg, const float f[NF])
 
 __device__ inline void write_empty_track(const TrackArgs &a, int i)
 {
+    if (!a.x) return;  // candidate-scoring mode writes no track slots
     a.x[i] = 0.0f;
     a.y[i] = 0.0f;
     a.tx[i] = 0.0f;
@@ -324,11 +329,13 @@ __device__ inline bool seed_frame(const DevGeom &G, float fsx, float fsy, float 
     return true;
 }
 
-// Best candidate through one UTbX hit (rank r3, LDS position p3): refined
-// windows in UTaX, UTaU, UTbV, the <= 4 candidates, their fits.
-__device__ inline void item_best(const DevGeom &G, const TrackArgs &a, const float *hu_s, const uint16_t *hidx_s,
-                                 const int *E, const SeedConst &sc, int r3, int p3, int &best_n, double &best_chi2,
-                                 int &best_c, int bp[4])
+// Every valid candidate through one UTbX hit (rank r3, LDS position p3), in
+// candidate-index order: refined windows in UTaX, UTaU, UTbV, the <= 4 option
+// tuples, their fits.  visit(n, c, alpha, beta, chi2, bp) is called for each.
+template <typename Visit>
+__device__ inline void item_candidates(const DevGeom &G, const TrackArgs &a, const float *hu_s,
+                                       const uint16_t *hidx_s, const int *E, const SeedConst &sc, int r3, int p3,
+                                       Visit &&visit)
 {
     const double rho3 = (double)hu_s[p3] - sc.c[3];
     int A[3][MAX_CLOSEST];
@@ -357,9 +364,6 @@ __device__ inline void item_best(const DevGeom &G, const TrackArgs &a, const flo
         A[L][1] = G.ncl[L] >= 2 ? p1k : -1;
         nA[L] = (A[L][0] >= 0 ? 1 : 0) + (A[L][1] >= 0 ? 1 : 0);
     }
-    best_n = 0;
-    best_chi2 = 0.0;
-    best_c = -1;
     double rho[4];
     rho[3] = rho3;
 #pragma unroll
@@ -382,25 +386,70 @@ __device__ inline void item_best(const DevGeom &G, const TrackArgs &a, const flo
                 rho[2] = p2 >= 0 ? (double)hu_s[p2] - sc.c[2] : 0.0;
                 double al, be, c2;
                 fit_residuals(G, mask, rho, al, be, c2);
-                if (n > best_n || (n == best_n && c2 < best_chi2)) {
-                    best_n = n;
-                    best_chi2 = c2;
-                    best_c = ((r3 * G.nw[0] + i0) * G.nw[1] + i1) * G.nw[2] + i2;
-                    bp[0] = p0;
-                    bp[1] = p1;
-                    bp[2] = p2;
-                    bp[3] = p3;
-                }
+                const int bp[4] = {p0, p1, p2, p3};
+                visit(n, ((r3 * G.nw[0] + i0) * G.nw[1] + i1) * G.nw[2] + i2, al, be, c2, bp);
             }
         }
     }
+}
+
+// Best candidate through one UTbX hit: more hits, then lower chi2, then lower index.
+__device__ inline void item_best(const DevGeom &G, const TrackArgs &a, const float *hu_s, const uint16_t *hidx_s,
+                                 const int *E, const SeedConst &sc, int r3, int p3, int &best_n, double &best_chi2,
+                                 int &best_c, int bp_out[4])
+{
+    best_n = 0;
+    best_chi2 = 0.0;
+    best_c = -1;
+    item_candidates(G, a, hu_s, hidx_s, E, sc, r3, p3,
+                    [&](int n, int c, double, double, double c2, const int bp[4]) {
+                        if (n > best_n || (n == best_n && c2 < best_chi2)) {
+                            best_n = n;
+                            best_chi2 = c2;
+                            best_c = c;
+#pragma unroll
+                            for (int L = 0; L < 4; ++L) bp_out[L] = bp[L];
+                        }
+                    });
+}
+
+// The float32 track record of a fitted candidate and (optionally) its ghost score.
+struct StoredTrack {
+    float x, y, tx, ty, qop, chi2, score;
+};
+
+__device__ inline StoredTrack stored_track(const TrackArgs &a, const DevGeom &G, int i, int n, double al, double be,
+                                           double c2, const float *hu_s, const int bp[4], bool score)
+{
+    const float fsx = a.sx[i], fsy = a.sy[i], fstx = a.stx[i], fsty = a.sty[i], fsq = a.sqop[i];
+    const double sx = fsx, sy = fsy, stx = fstx, sty = fsty;
+    StoredTrack t;
+    t.x = (float)(fma(stx, G.zref_seed, sx) + al);
+    t.tx = (float)(stx + be);
+    t.y = (float)fma(sty, G.zref_seed, sy);
+    t.ty = fsty;
+    t.qop = (G.mk != 0.0) ? (float)(-be / G.mk) : fsq;
+    t.chi2 = (float)c2;
+    t.score = 0.0f;
+    if (score) {
+        float hu4[4];
+        int mask = 0;
+#pragma unroll
+        for (int L = 0; L < 4; ++L) {
+            hu4[L] = bp[L] >= 0 ? hu_s[bp[L]] : 0.0f;
+            mask |= bp[L] >= 0 ? (1 << L) : 0;
+        }
+        float f[NF];
+        ghost_features(G, t.x, t.y, t.tx, t.ty, t.qop, t.chi2, n, fsx, fsy, fstx, fsty, fsq, hu4, mask, f);
+        t.score = mlp_score(a.W, f);
+    }
+    return t;
 }
 
 // Write the selected candidate (LDS positions bp, -1 = none) as seed i's track.
 __device__ inline void write_track(const TrackArgs &a, const DevGeom &G, int i, const SeedConst &sc,
                                    const float *hu_s, const uint16_t *hidx_s, const int bp[4], int c)
 {
-    const float fsx = a.sx[i], fsy = a.sy[i], fstx = a.stx[i], fsty = a.sty[i], fsq = a.sqop[i];
     const int mask = (bp[0] >= 0 ? 1 : 0) | (bp[1] >= 0 ? 2 : 0) | (bp[2] >= 0 ? 4 : 0) | 8;
     const int n = __popc(mask);
     double rho[4];
@@ -408,33 +457,43 @@ __device__ inline void write_track(const TrackArgs &a, const DevGeom &G, int i, 
     for (int L = 0; L < 4; ++L) rho[L] = bp[L] >= 0 ? (double)hu_s[bp[L]] - sc.c[L] : 0.0;
     double al, be, c2;
     fit_residuals(G, mask, rho, al, be, c2);
-    const double sx = fsx, sy = fsy, stx = fstx, sty = fsty;
-    const float xf = (float)(fma(stx, G.zref_seed, sx) + al);
-    const float txf = (float)(stx + be);
-    const float yf = (float)fma(sty, G.zref_seed, sy);
-    const float tyf = fsty;
-    const float qf = (G.mk != 0.0) ? (float)(-be / G.mk) : fsq;
-    const float c2f = (float)c2;
-    a.x[i] = xf;
-    a.y[i] = yf;
-    a.tx[i] = txf;
-    a.ty[i] = tyf;
-    a.qop[i] = qf;
-    a.chi2[i] = c2f;
+    const StoredTrack t = stored_track(a, G, i, n, al, be, c2, hu_s, bp, a.fuse_mlp != 0);
+    a.x[i] = t.x;
+    a.y[i] = t.y;
+    a.tx[i] = t.tx;
+    a.ty[i] = t.ty;
+    a.qop[i] = t.qop;
+    a.chi2[i] = t.chi2;
     a.h0[i] = bp[0] >= 0 ? (int)hidx_s[bp[0]] : -1;
     a.h1[i] = bp[1] >= 0 ? (int)hidx_s[bp[1]] : -1;
     a.h2[i] = bp[2] >= 0 ? (int)hidx_s[bp[2]] : -1;
     a.h3[i] = (int)hidx_s[bp[3]];
     a.nhits[i] = n;
     if (a.cand) a.cand[i] = c;
-    if (a.fuse_mlp) {
-        float hu4[4];
-#pragma unroll
-        for (int L = 0; L < 4; ++L) hu4[L] = bp[L] >= 0 ? hu_s[bp[L]] : 0.0f;
-        float f[NF];
-        ghost_features(G, xf, yf, txf, tyf, qf, c2f, n, fsx, fsy, fstx, fsty, fsq, hu4, mask, f);
-        a.score[i] = mlp_score(a.W, f);
-    }
+    if (a.fuse_mlp) a.score[i] = t.score;
+}
+
+// One row per (seed, candidate index) of the candidate-scoring mode.
+__device__ inline void write_candidate_row(const TrackArgs &a, const DevGeom &G, int i, int n, int c, double al,
+                                           double be, double c2, const float *hu_s, const uint16_t *hidx_s,
+                                           const int bp[4])
+{
+    const StoredTrack t = stored_track(a, G, i, n, al, be, c2, hu_s, bp, true);
+    const size_t r = (size_t)i * (size_t)a.cmax + (size_t)c;
+    a.r_seed[r] = i;
+    a.r_cand[r] = c;
+    a.r_nhits[r] = n;
+    a.r_h0[r] = bp[0] >= 0 ? (int)hidx_s[bp[0]] : -1;
+    a.r_h1[r] = bp[1] >= 0 ? (int)hidx_s[bp[1]] : -1;
+    a.r_h2[r] = bp[2] >= 0 ? (int)hidx_s[bp[2]] : -1;
+    a.r_h3[r] = (int)hidx_s[bp[3]];
+    a.r_x[r] = t.x;
+    a.r_y[r] = t.y;
+    a.r_tx[r] = t.tx;
+    a.r_ty[r] = t.ty;
+    a.r_qop[r] = t.qop;
+    a.r_chi2[r] = t.chi2;
+    a.r_score[r] = t.score;
 }
 
 // Stage one event's hits into LDS, bucketed by (layer, bin); the order inside a
@@ -515,7 +574,7 @@ __device__ inline bool stage_hits(const TrackArgs &a, int hb, const int hl[4], i
     return true;
 }
 
-template <int BLOCK>
+template <int BLOCK, bool CANDS>
 __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -638,6 +697,13 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
                 const uint32_t d = it_desc[it];
                 const int sl = (int)(d >> 20), r3 = (int)((d >> 16) & 15u), p3 = (int)(d & 0xffffu);
                 const SeedConst scs = s_c[sl];
+                if (CANDS) {
+                    item_candidates(G, a, hu_s, hidx_s, E, scs, r3, p3,
+                                    [&](int n, int c, double al, double be, double c2, const int bp[4]) {
+                                        write_candidate_row(a, G, sc0 + sl, n, c, al, be, c2, hu_s, hidx_s, bp);
+                                    });
+                    continue;
+                }
                 int bn, bc, bp[4] = {-1, -1, -1, -1};
                 double bchi2;
                 item_best(G, a, hu_s, hidx_s, E, scs, r3, p3, bn, bchi2, bc, bp);
@@ -653,7 +719,7 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
             }
             __syncthreads();
             // phase C: lane per seed, write the winner (and its ghost score)
-            if (tid < nacc) {
+            if (!CANDS && tid < nacc) {
                 const unsigned long long key = s_key[tid];
                 if (key == ~0ull) {
                     write_empty_track(a, i);
@@ -682,6 +748,13 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
             __threadfence();
         }
     }
+}
+
+// Marks every candidate row empty (nhits 0) before a candidate-scoring pass.
+__global__ void k_clear_rows(int *r_nhits, long long n)
+{
+    for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
+        r_nhits[k] = 0;
 }
 
 // Standalone ghost-killer: one workgroup per event (grid-stride), lane per seed.

@@ -23,7 +23,8 @@ DS_F_BAD_OFFSETS, DS_F_CAPACITY, DS_F_NONFINITE = 1, 2, 4
 N_WEIGHTS = 1121
 
 EXPORTED = ("ds_create", "ds_destroy", "ds_load_geometry", "ds_find_tracks", "ds_ghost_kill", "ds_kill_clones",
-            "ds_vertex", "ds_process", "ds_set_launch", "ds_get_launch", "ds_status_str")
+            "ds_candidate_slots", "ds_score_candidates", "ds_vertex", "ds_process", "ds_set_launch",
+            "ds_get_launch", "ds_status_str")
 
 
 class DsGeometry(C.Structure):
@@ -78,6 +79,17 @@ class DsVertices(C.Structure):
     ]
 
 
+class DsCandidates(C.Structure):
+    _fields_ = [
+        ("capacity", C.c_int32),
+        ("seed", C.c_void_p), ("cand", C.c_void_p), ("nhits", C.c_void_p),
+        ("hit", C.c_void_p * 4),
+        ("x", C.c_void_p), ("y", C.c_void_p), ("tx", C.c_void_p), ("ty", C.c_void_p),
+        ("qop", C.c_void_p), ("chi2", C.c_void_p), ("score", C.c_void_p),
+        ("flags", C.c_void_p),
+    ]
+
+
 _lib = None
 
 
@@ -96,6 +108,8 @@ def library() -> C.CDLL:
         lib.ds_find_tracks.argtypes = [P, C.POINTER(DsEvents), C.POINTER(DsTracks), C.c_int, C.c_int, P]
         lib.ds_ghost_kill.argtypes = [P, C.POINTER(DsEvents), C.POINTER(DsTracks), P]
         lib.ds_kill_clones.argtypes = [P, C.POINTER(DsEvents), C.POINTER(DsTracks), P]
+        lib.ds_candidate_slots.argtypes = [P]
+        lib.ds_score_candidates.argtypes = [P, C.POINTER(DsEvents), C.POINTER(DsCandidates), P]
         lib.ds_vertex.argtypes = [P, C.POINTER(DsEvents), C.POINTER(DsTracks), C.c_float, C.POINTER(DsVertices),
                                   C.c_int, P]
         lib.ds_process.argtypes = [P, C.POINTER(DsEvents), C.POINTER(DsTracks), C.c_float, C.POINTER(DsVertices),
@@ -278,6 +292,46 @@ def ds_ghost_kill(ctx, ev: DeviceEvents, trk: DeviceTracks, stream=None) -> None
 def ds_kill_clones(ctx, ev: DeviceEvents, trk: DeviceTracks, stream=None) -> None:
     _check(library().ds_kill_clones(ctx, C.byref(ev.struct), C.byref(trk.struct), _stream_handle(stream)),
            "ds_kill_clones")
+
+
+class DeviceCandidates:
+    """Candidate rows (n_seeds * slots) and the ds_candidates struct."""
+
+    def __init__(self, n_seeds: int, slots: int, device="cuda"):
+        import torch
+        dev = torch.device(device)
+        self.n_seeds, self.slots = int(n_seeds), int(slots)
+        n = max(self.n_seeds * self.slots, 1)
+        for k in ("seed", "cand", "nhits"):
+            setattr(self, k, torch.zeros(n, dtype=torch.int32, device=dev))
+        self.hits = torch.full((4, n), -1, dtype=torch.int32, device=dev)
+        for k in ("x", "y", "tx", "ty", "qop", "chi2", "score"):
+            setattr(self, k, torch.zeros(n, dtype=torch.float32, device=dev))
+        self.flags = torch.zeros(1, dtype=torch.int32, device=dev)
+        s = DsCandidates()
+        s.capacity = self.n_seeds * self.slots
+        for k in ("seed", "cand", "nhits", "x", "y", "tx", "ty", "qop", "chi2", "score", "flags"):
+            setattr(s, k, _ptr(getattr(self, k)))
+        for L in range(4):
+            s.hit[L] = _ptr(self.hits[L])
+        self.struct = s
+
+    def to_numpy(self) -> Dict[str, np.ndarray]:
+        m = self.n_seeds * self.slots
+        out = {k: getattr(self, k)[:m].cpu().numpy() for k in ("seed", "cand", "nhits", "x", "y", "tx", "ty", "qop",
+                                                              "chi2", "score")}
+        out["hits"] = self.hits[:, :m].cpu().numpy().T.copy()
+        out["flags"] = int(self.flags.item())
+        return out
+
+
+def ds_candidate_slots(ctx) -> int:
+    return int(library().ds_candidate_slots(ctx))
+
+
+def ds_score_candidates(ctx, ev: DeviceEvents, cands: DeviceCandidates, stream=None) -> None:
+    _check(library().ds_score_candidates(ctx, C.byref(ev.struct), C.byref(cands.struct), _stream_handle(stream)),
+           "ds_score_candidates")
 
 
 def ds_vertex(ctx, ev: DeviceEvents, trk: DeviceTracks, score_max: float, vtx: DeviceVertices,

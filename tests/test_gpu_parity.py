@@ -349,3 +349,34 @@ def test_clone_killing_matches_oracle():
     finally:
         torch.cuda.synchronize()
         c.close()
+
+
+def test_every_candidate_scored_matches_oracle():
+    g = synth.default_geometry(loose=True)
+    c = ds.Context(0, g, W)
+    try:
+        b = synth.generate(1, n_events=20, geometry=g, seed=8)
+        slots = ds.ds_candidate_slots(c.handle)
+        assert slots == 40
+        ev = ds.DeviceEvents(b)
+        cd = ds.DeviceCandidates(b.n_seeds, slots)
+        ds.ds_score_candidates(c.handle, ev, cd)
+        torch.cuda.synchronize()
+        got = cd.to_numpy()
+        ref = O.score_candidates(b, g, W)
+        rows = ref["seed"].astype(np.int64) * slots + ref["cand"]
+        present = np.zeros(b.n_seeds * slots, bool)
+        present[rows] = True
+        assert np.all(got["nhits"][~present] == 0)
+        same = (got["nhits"][rows] == ref["nhits"]) & np.all(got["hits"][rows] == ref["hits"], axis=1)
+        assert same.mean() >= 0.9999, same.mean()
+        ok = rows[same]
+        st = np.stack([got[k][ok] for k in ("x", "y", "tx", "ty", "qop", "chi2")], 1).astype(np.float64)
+        rs = ref["state"][same]
+        floors = np.array([1.0, 1.0, 1e-3, 1e-3, 1e-2, 1.0])
+        assert np.max(np.abs(st - rs) / np.maximum(np.abs(rs), floors)) <= 1e-4
+        assert np.max(np.abs(got["score"][ok] - ref["score"][same])) <= 1e-5
+        say(f"[parity] candidate rows: {len(rows)} rows, identical {same.mean():.6f}")
+    finally:
+        torch.cuda.synchronize()
+        c.close()

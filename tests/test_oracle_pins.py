@@ -514,3 +514,30 @@ def test_clone_killing_on_generated_events_removes_few():
         assert any(j != i and st["nhits"][j] > 0 and
                    sum(st["hits"][i, L] >= 0 and st["hits"][i, L] == st["hits"][j, L] for L in range(4)) > 2
                    for j in js)
+
+
+# ------------------------------------------------- every candidate scored -----
+
+def test_candidate_rows_are_the_valid_candidates_and_include_the_track():
+    g = synth.default_geometry(loose=True)
+    b = synth.generate(1, n_events=3, geometry=g, seed=4)
+    w = synth.mlp_weights()
+    rows = O.score_candidates(b, g, w)
+    res = O.run_path(b, g, w, score_max=np.inf)
+    tr = res["tracks"]
+    k = 0
+    for e in range(b.n_events):
+        layers = [b.hu[b.hit_off[4 * e + L]:b.hit_off[4 * e + L + 1]].astype(np.float64) for L in range(4)]
+        for i in range(b.seed_off[e], b.seed_off[e + 1]):
+            seed = [float(v[i]) for v in (b.sx, b.sy, b.stx, b.sty, b.sqop)]
+            cands = O.candidates(g, seed, layers)
+            valid = np.nonzero(cands["valid"])[0]
+            for j in valid:
+                assert rows["seed"][k] == i and rows["cand"][k] == cands["c"][j]
+                assert list(rows["hits"][k]) == list(cands["hits"][j])
+                if rows["cand"][k] == tr["cand"][i]:
+                    st = [res["stored"][q][i] for q in ("x", "y", "tx", "ty", "qop", "chi2")]
+                    assert np.array_equal(rows["state"][k], np.array(st, np.float64))
+                    assert rows["score"][k] == res["score"][i]
+                k += 1
+    assert k == len(rows["seed"]) and k > 1000
