@@ -155,6 +155,11 @@ typedef struct {
  * seed slots within the event.  count[n_events]; i, j, x, y, z, doca
  * [n_events*cap_per_event].  overflow [1]: number of vertices dropped beyond
  * the cap, added to (never cleared by the library).  flags [1]: OR-ed.
+ * m_pipi, m_ppi, line[4] (all or none; nullable; need ds_load_lines): the
+ * pair's invariant mass in MeV under the pi+ pi- and p pi (faster track =
+ * proton) hypotheses, from the seed momenta and the trajectory tangents at
+ * the points of closest approach (mass after the vertex correction, Fig. 18),
+ * and the four trigger-line network responses ("Expected Physics Impact").
  */
 typedef struct {
     int32_t cap_per_event;
@@ -163,6 +168,8 @@ typedef struct {
     float *x, *y, *z, *doca;
     int32_t *overflow;
     int32_t *flags;
+    float *m_pipi, *m_ppi;
+    float *line[4];
 } ds_vertices;
 
 /*
@@ -195,6 +202,16 @@ void ds_destroy(ds_ctx *ctx);
  * output).  Copied to device memory, which stays resident.  Synchronous.
  */
 ds_status ds_load_geometry(ds_ctx *ctx, const ds_geometry *g, const float *mlp_weights, size_t n_weights);
+
+/*
+ * Load the four trigger-line networks ("Expected Physics Impact": one hidden
+ * layer of 32 nodes, one output): a HOST array of 4 x 449 floats, each
+ * W1[32][12], b1[32], W2[1][32], b2[1] row-major; ReLU hidden, sigmoid out.
+ * Inputs per vertex: ln p1, ln p2 (GeV), the two tracks' tangent slopes
+ * (dx/dz, dy/dz)/0.3 at the vertex, z/1000, transverse radius/100, DOCA,
+ * (m_pipi - 497.6)/100, (m_ppi - 1115.7)/100, pair pT (GeV).  Synchronous.
+ */
+ds_status ds_load_lines(ds_ctx *ctx, const float *line_weights, size_t n_weights);
 
 /*
  * Track finding ("The Downstream Algorithm", Dv0): one track slot per seed.

@@ -657,6 +657,61 @@ int orc_pca(const orc_geom *g, const double *t1, const double *t2, int iters, do
     return 1;
 }
 
+/* ---------------------------------------------- mass and trigger lines ---- */
+
+#define LINE_NF 12
+#define LINE_NH 32
+#define LINE_NW (LINE_NH * LINE_NF + LINE_NH + LINE_NH + 1) /* 449 per line network */
+
+/* After vertexing ("Vertexing Two Downstream Tracks"; mass after the vertex
+ * correction, Fig. 18; "Expected Physics Impact": four one-hidden-layer
+ * networks of 32 nodes over the two tracks and the vertex).  Momenta: |p| =
+ * 1/|q/p| of each track's seed, direction = trajectory tangent at its point of
+ * closest approach (z1, z2).  Masses in MeV: K0S hypothesis pi+ pi-, Lambda
+ * hypothesis p pi with the proton the higher-momentum track.  Line inputs
+ * (reading; the paper does not list them): ln p1, ln p2 (GeV), the four
+ * tangent slopes, vertex z/1000, transverse radius/100, DOCA, (m_pipi -
+ * 497.6)/100, (m_ppi - 1115.7)/100, pair pT (GeV).  out = m_pipi, m_ppi, s0..s3. */
+void orc_vertex_extras(const orc_geom *g, const double *t1, const double *t2, double q1, double q2, double z1,
+                       double z2, const double *vtx /* x y z doca */, const double *wl, double *out)
+{
+    const double MPI = 0.13957039, MP = 0.93827209;
+    double fp = g->fringe_polarity;
+    double gam1 = -fp * (g->gamma_c0 + g->gamma_c1 * (t1[4] * 1e-3));
+    double gam2 = -fp * (g->gamma_c0 + g->gamma_c1 * (t2[4] * 1e-3));
+    double a1 = z1 - g->z_ref, a2 = z2 - g->z_ref;
+    double d1[3] = {t1[2] + 2.0 * gam1 * a1, t1[3], 1.0}, d2[3] = {t2[2] + 2.0 * gam2 * a2, t2[3], 1.0};
+    double n1 = sqrt(dot3(d1, d1)), n2 = sqrt(dot3(d2, d2));
+    double p1 = 1.0 / fabs(q1), p2 = 1.0 / fabs(q2);
+    double P1[3], P2[3], S[3];
+    for (int k = 0; k < 3; ++k) {
+        P1[k] = p1 * d1[k] / n1;
+        P2[k] = p2 * d2[k] / n2;
+        S[k] = P1[k] + P2[k];
+    }
+    double ss = dot3(S, S);
+    double e1 = sqrt(p1 * p1 + MPI * MPI), e2 = sqrt(p2 * p2 + MPI * MPI);
+    double m2 = (e1 + e2) * (e1 + e2) - ss;
+    out[0] = 1000.0 * sqrt(m2 > 0.0 ? m2 : 0.0);
+    double ep = p1 >= p2 ? sqrt(p1 * p1 + MP * MP) + e2 : sqrt(p2 * p2 + MP * MP) + e1;
+    m2 = ep * ep - ss;
+    out[1] = 1000.0 * sqrt(m2 > 0.0 ? m2 : 0.0);
+    double f[LINE_NF] = {log(p1), log(p2), d1[0] / 0.3, d1[1] / 0.3, d2[0] / 0.3, d2[1] / 0.3, vtx[2] / 1000.0,
+                         sqrt(vtx[0] * vtx[0] + vtx[1] * vtx[1]) / 100.0, vtx[3], (out[0] - 497.6) / 100.0,
+                         (out[1] - 1115.7) / 100.0, sqrt(S[0] * S[0] + S[1] * S[1])};
+    for (int l = 0; l < 4; ++l) {
+        const double *W = wl + (size_t)l * LINE_NW, *b1 = W + LINE_NH * LINE_NF, *w2 = b1 + LINE_NH,
+                     *b2 = w2 + LINE_NH;
+        double z = b2[0];
+        for (int j = 0; j < LINE_NH; ++j) {
+            double a = b1[j];
+            for (int k = 0; k < LINE_NF; ++k) a += W[j * LINE_NF + k] * f[k];
+            z += w2[j] * (a > 0.0 ? a : 0.0);
+        }
+        out[2 + l] = 1.0 / (1.0 + exp(-z));
+    }
+}
+
 /* Vertices of every event: pairs i < j (seed slots within the event) of kept
  * tracks (nhits > 0, score < score_max) with opposite seed charge, PCA by
  * orc_pca with g->newton_iters steps, kept if DOCA < doca_max.  Output is
@@ -665,7 +720,8 @@ int orc_pca(const orc_geom *g, const double *t1, const double *t2, int iters, do
 int orc_vertex(const orc_geom *g, int n_events, const int *seed_off, const double *sqop, const double *x,
                const double *y, const double *tx, const double *ty, const double *qop, const double *score,
                const int *nhits, double score_max, int cap, int *count, int *vi, int *vj, double *vx, double *vy,
-               double *vz, double *vdoca, double *vopen, long long *overflow)
+               double *vz, double *vdoca, double *vopen, long long *overflow, const double *line_w,
+               double *extras /* nullable [E*cap*6] */)
 {
     long long ovf = 0;
     for (int e = 0; e < n_events; ++e) {
@@ -692,6 +748,8 @@ int orc_vertex(const orc_geom *g, int n_events, const int *seed_off, const doubl
                     double d1[3] = {tx[i], ty[i], 1.0}, d2[3] = {tx[j], ty[j], 1.0}, c[3];
                     cross3(d1, d2, c);
                     vopen[k] = sqrt(dot3(c, c));
+                    if (extras && line_w)
+                        orc_vertex_extras(g, t1, t2, sqop[i], sqop[j], o[4], o[5], o, line_w, extras + 6 * k);
                 } else {
                     ++ovf;
                 }

@@ -198,7 +198,7 @@ def ghost_kill(batch, st: dict, g: dict, weights, want_features: bool = False):
     return (score, feats) if want_features else score
 
 
-def vertex(seed_off, sqop, st: dict, score, g: dict, score_max: float, cap: int) -> dict:
+def vertex(seed_off, sqop, st: dict, score, g: dict, score_max: float, cap: int, line_weights=None) -> dict:
     """Vertices (O10) of stored tracks; event-major, (i, j)-ordered, capped."""
     L = lib()
     E = len(seed_off) - 1
@@ -218,12 +218,17 @@ def vertex(seed_off, sqop, st: dict, score, g: dict, score_max: float, cap: int)
     vx, vy, vz, vd, vo = (np.zeros(n, np.float64) for _ in range(5))
     ovf = C.c_longlong(0)
     geom = make_geom(g)
+    extras = np.zeros((n, 6)) if line_weights is not None else None
     L.orc_vertex(C.byref(geom), C.c_int(E), so_p, d(sqop), d(st["x"]), d(st["y"]), d(st["tx"]), d(st["ty"]),
                  d(st["qop"]), d(score), nh_p, C.c_double(score_max), C.c_int(cap), count.ctypes.data_as(_ip),
                  vi.ctypes.data_as(_ip), vj.ctypes.data_as(_ip), vx.ctypes.data_as(_dp), vy.ctypes.data_as(_dp),
-                 vz.ctypes.data_as(_dp), vd.ctypes.data_as(_dp), vo.ctypes.data_as(_dp), C.byref(ovf))
-    return dict(count=count[:E], i=vi, j=vj, x=vx, y=vy, z=vz, doca=vd, opening=vo, overflow=int(ovf.value),
-                cap=cap)
+                 vz.ctypes.data_as(_dp), vd.ctypes.data_as(_dp), vo.ctypes.data_as(_dp), C.byref(ovf),
+                 d(line_weights) if line_weights is not None else None,
+                 extras.ctypes.data_as(_dp) if extras is not None else None)
+    out = dict(count=count[:E], i=vi, j=vj, x=vx, y=vy, z=vz, doca=vd, opening=vo, overflow=int(ovf.value), cap=cap)
+    if extras is not None:
+        out["m_pipi"], out["m_ppi"], out["lines"] = extras[:, 0], extras[:, 1], extras[:, 2:6]
+    return out
 
 
 def vertex_list(v: dict):
@@ -307,6 +312,17 @@ def pca(g: dict, t1, t2, iters=None):
     ok = L.orc_pca(C.byref(geom), p1, p2, C.c_int(g["newton_iters"] if iters is None else iters),
                    out.ctypes.data_as(_dp))
     return out if ok else None
+
+
+def vertex_extras(g: dict, t1, t2, q1, q2, z1, z2, vtx, line_weights):
+    L = lib()
+    keep = [np.ascontiguousarray(v, dtype=np.float64) for v in (t1, t2, vtx, line_weights)]
+    out = np.zeros(6)
+    geom = make_geom(g)
+    L.orc_vertex_extras(C.byref(geom), *[k.ctypes.data_as(_dp) for k in keep[:2]], C.c_double(q1), C.c_double(q2),
+                        C.c_double(z1), C.c_double(z2), keep[2].ctypes.data_as(_dp), keep[3].ctypes.data_as(_dp),
+                        out.ctypes.data_as(_dp))
+    return out
 
 
 def mlp(weights, f) -> float:

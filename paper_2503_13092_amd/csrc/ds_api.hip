@@ -46,6 +46,7 @@ struct ds_ctx {
     double ghost_threshold = 0.5;
     bool clone_kill = false;
     float *d_W = nullptr;
+    float *d_WL = nullptr;   // trigger-line networks
     int *d_counters = nullptr;  // [MAX_STREAM_SLOTS][4]
     std::map<void *, int> slots;
     Launch trk{256, 4, 512};
@@ -74,7 +75,7 @@ size_t track_lds(int hcap, int nb, int block, int icap)
     return off + (size_t)icap * 8;
 }
 
-size_t vertex_lds(int tcap, int block) { return ((size_t)tcap * 24 + (size_t)64 * VTX_PPT * 24) * (size_t)(block / 64); }
+size_t vertex_lds(int tcap, int block) { return ((size_t)tcap * 24 + (size_t)64 * VTX_PPT * 32) * (size_t)(block / 64); }
 
 int round_up(int v, int m) { return ((v + m - 1) / m) * m; }
 
@@ -104,6 +105,14 @@ ds_status check_events(const ds_events *ev)
     if (ev->n_seeds > 0 && (!ev->sx || !ev->sy || !ev->stx || !ev->sty || !ev->sqop)) return DS_E_ARG;
     if (ev->n_hits > 0 && !ev->hu) return DS_E_ARG;
     return DS_OK;
+}
+
+ds_status check_extras(const ds_ctx *c, const ds_vertices *v)
+{
+    const bool any = v->m_pipi || v->m_ppi || v->line[0] || v->line[1] || v->line[2] || v->line[3];
+    if (!any) return DS_OK;
+    if (!(v->m_pipi && v->m_ppi && v->line[0] && v->line[1] && v->line[2] && v->line[3])) return DS_E_ARG;
+    return c->d_WL ? DS_OK : DS_E_STATE;
 }
 
 ds_status check_tracks(const ds_tracks *t, int n_seeds, bool need_score)
@@ -289,6 +298,13 @@ ds_status plan_vertex(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, floa
     a.counter = counters + 2;
     a.ev_single = -1;
     a.tcap = tcap;
+    a.m_pipi = out->m_pipi;
+    a.m_ppi = out->m_ppi;
+    a.line0 = out->line[0];
+    a.line1 = out->line[1];
+    a.line2 = out->line[2];
+    a.line3 = out->line[3];
+    a.WL = c->d_WL;
     p->block = c->vtx.block;
     p->grid = std::max(1, std::min(ev->n_events, c->n_cu * c->vtx.wg_per_cu));
     p->lds = lds;
@@ -499,6 +515,7 @@ void ds_destroy(ds_ctx *c)
         (void)hipGraphDestroy(g.second.graph);
     }
     if (c->d_W) (void)hipFree(c->d_W);
+    if (c->d_WL) (void)hipFree(c->d_WL);
     if (c->d_counters) (void)hipFree(c->d_counters);
     if (c->capture) (void)hipStreamDestroy(c->capture);
     delete c;
@@ -708,6 +725,8 @@ ds_status ds_vertex(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, float 
     if (!out->count) return DS_E_ARG;
     if (out->cap_per_event > 0 && (!out->i || !out->j || !out->x || !out->y || !out->z || !out->doca))
         return DS_E_ARG;
+    st = check_extras(c, out);
+    if (st != DS_OK) return st;
     std::lock_guard<std::mutex> lock(c->mu);
     if (hipSetDevice(c->device) != hipSuccess) return DS_E_DEVICE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -736,6 +755,8 @@ ds_status ds_process(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, float
     if (!out->count) return DS_E_ARG;
     if (out->cap_per_event > 0 && (!out->i || !out->j || !out->x || !out->y || !out->z || !out->doca))
         return DS_E_ARG;
+    st = check_extras(c, out);
+    if (st != DS_OK) return st;
     if (std::isnan(score_max)) score_max = (float)c->ghost_threshold;
     std::lock_guard<std::mutex> lock(c->mu);
     if (hipSetDevice(c->device) != hipSuccess) return DS_E_DEVICE;
@@ -770,6 +791,17 @@ ds_status ds_process(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, float
         }
         return run_vertex(c, vp, mode, ss);
     });
+}
+
+ds_status ds_load_lines(ds_ctx *c, const float *w, size_t nw)
+{
+    if (!c || !w || nw != (size_t)(4 * ds::LINE_NW)) return DS_E_ARG;
+    std::lock_guard<std::mutex> lock(c->mu);
+    if (hipSetDevice(c->device) != hipSuccess) return DS_E_DEVICE;
+    if (!c->d_WL && hipMalloc(&c->d_WL, sizeof(float) * 4 * ds::LINE_NW) != hipSuccess) return DS_E_NOMEM;
+    if (hipMemcpy(c->d_WL, w, sizeof(float) * 4 * ds::LINE_NW, hipMemcpyHostToDevice) != hipSuccess)
+        return DS_E_DEVICE;
+    return DS_OK;
 }
 
 ds_status ds_set_launch(ds_ctx *c, int kernel, int block, int wg_per_cu, int bins)

@@ -32,6 +32,8 @@ constexpr int NWEIGHTS = NH1 * NF + NH1 + NH2 * NH1 + NH2 + NH2 + 1;  // 1121
 constexpr int MAX_L3 = 16;
 constexpr int MAX_CLOSEST = 2;
 constexpr int F_BAD_OFFSETS = 1, F_CAPACITY = 2, F_NONFINITE = 4;
+constexpr int LINE_NF = 12, LINE_NH = 32;
+constexpr int LINE_NW = LINE_NH * LINE_NF + LINE_NH + LINE_NH + 1;  // 449 per network
 
 // Geometry after host-side preprocessing (passed by value as a kernel argument).
 struct DevGeom {
@@ -112,6 +114,9 @@ struct VertexArgs {
     int *counter;        // [0] next event, [1] finished workgroups
     int ev_single;
     int tcap;            // LDS capacity for kept tracks
+    // after-vertex outputs (nullable): masses (MeV) and the four trigger-line scores
+    float *m_pipi, *m_ppi, *line0, *line1, *line2, *line3;
+    const float *WL;     // trigger-line networks, 4 x (W1[32][12], b1[32], W2[32], b2)
 };
 
 // ----------------------------------------------------------------- helpers
@@ -815,7 +820,7 @@ __global__ __launch_bounds__(BLOCK) void k_ghost(GhostArgs a, DevGeom G)
 // a singular Newton system.
 __device__ inline bool pca64(const DevGeom &G, double x1, double y1, double tx1, double ty1, double g1, double x2,
                              double y2, double tx2, double ty2, double g2, double &vx, double &vy, double &vz,
-                             double &doca)
+                             double &doca, double &s_out, double &t_out)
 {
     const double wx = x1 - x2, wy = y1 - y2;
     const double nx = ty1 - ty2, ny = tx2 - tx1, nz = tx1 * ty2 - ty1 * tx2;
@@ -852,6 +857,8 @@ __device__ inline bool pca64(const DevGeom &G, double x1, double y1, double tx1,
     vy = 0.5 * (Y1 + Y2);
     vz = G.zref + 0.5 * (s + t);
     doca = sqrt(Dx * Dx + Dy * Dy + Dz * Dz);
+    s_out = s;
+    t_out = t;
     return true;
 }
 
@@ -866,6 +873,59 @@ __device__ inline void unrank_pair(int k, int n, int &pa, int &pb)
     while (r > 0 && start(r) > k) --r;
     pa = r;
     pb = k - start(r) + r + 1;
+}
+
+// Invariant masses of a vertex (pi+ pi-, and p pi with the faster track as the
+// proton; MeV) from the seed momenta and the trajectory tangents at the points
+// of closest approach (offsets s, t from z_ref), then the four trigger-line
+// networks (12 -> 32 ReLU -> 1 sigmoid, float32) on the pair and the vertex.
+__device__ inline void vertex_extras(const DevGeom &G, const float *WLg, float4 A, float4 B, double g1, double g2,
+                                     float q1, float q2, double s, double t, float4 V, float out[6])
+{
+    const double MPI = 0.13957039, MPR = 0.93827209;
+    const double d1x = (double)A.z + 2.0 * g1 * s, d1y = A.w, d2x = (double)B.z + 2.0 * g2 * t, d2y = B.w;
+    const double n1 = sqrt(d1x * d1x + d1y * d1y + 1.0), n2 = sqrt(d2x * d2x + d2y * d2y + 1.0);
+    const double p1 = 1.0 / fabs((double)q1), p2 = 1.0 / fabs((double)q2);
+    const double Sx = p1 * d1x / n1 + p2 * d2x / n2;
+    const double Sy = p1 * d1y / n1 + p2 * d2y / n2;
+    const double Sz = p1 / n1 + p2 / n2;
+    const double ss = Sx * Sx + Sy * Sy + Sz * Sz;
+    const double e1 = sqrt(p1 * p1 + MPI * MPI), e2 = sqrt(p2 * p2 + MPI * MPI);
+    double m2 = (e1 + e2) * (e1 + e2) - ss;
+    const double mpipi = 1000.0 * sqrt(m2 > 0.0 ? m2 : 0.0);
+    const double ep = p1 >= p2 ? sqrt(p1 * p1 + MPR * MPR) + e2 : sqrt(p2 * p2 + MPR * MPR) + e1;
+    m2 = ep * ep - ss;
+    const double mppi = 1000.0 * sqrt(m2 > 0.0 ? m2 : 0.0);
+    out[0] = (float)mpipi;
+    out[1] = (float)mppi;
+    float f[LINE_NF];
+    f[0] = (float)log(p1);
+    f[1] = (float)log(p2);
+    f[2] = (float)(d1x / 0.3);
+    f[3] = (float)(d1y / 0.3);
+    f[4] = (float)(d2x / 0.3);
+    f[5] = (float)(d2y / 0.3);
+    f[6] = V.z * 1e-3f;
+    f[7] = sqrtf(V.x * V.x + V.y * V.y) * 0.01f;
+    f[8] = V.w;
+    f[9] = (float)((mpipi - 497.6) * 0.01);
+    f[10] = (float)((mppi - 1115.7) * 0.01);
+    f[11] = (float)sqrt(Sx * Sx + Sy * Sy);
+    asm volatile("" : "+s"(WLg));
+    cfloat *WL = (cfloat *)(WLg);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        cfloat *W = WL + l * LINE_NW, *b1 = W + LINE_NH * LINE_NF, *w2 = b1 + LINE_NH, *b2 = w2 + LINE_NH;
+        float z = b2[0];
+#pragma unroll
+        for (int j = 0; j < LINE_NH; ++j) {
+            float a = b1[j];
+#pragma unroll
+            for (int k = 0; k < LINE_NF; ++k) a = fmaf(W[j * LINE_NF + k], f[k], a);
+            z = fmaf(w2[j], fmaxf(a, 0.0f), z);
+        }
+        out[2 + l] = 1.0f / (1.0f + __expf(-z));
+    }
 }
 
 __device__ inline void wave_sync()
@@ -900,7 +960,7 @@ __global__ __launch_bounds__(BLOCK) void k_vertex(VertexArgs a, DevGeom G)
     constexpr int CH = 64 * PPT;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const size_t wave_bytes = (size_t)a.tcap * 24 + (size_t)CH * 24;
+    const size_t wave_bytes = (size_t)a.tcap * 24 + (size_t)CH * 32;
     unsigned char *wb = smem + (size_t)wid * wave_bytes;
     float4 *st = reinterpret_cast<float4 *>(wb);                                   // x, y, tx, ty
     float *sq = reinterpret_cast<float *>(wb + (size_t)a.tcap * 16);               // track q/p
@@ -908,7 +968,9 @@ __global__ __launch_bounds__(BLOCK) void k_vertex(VertexArgs a, DevGeom G)
     int *qk = reinterpret_cast<int *>(wb + (size_t)a.tcap * 24);                   // survivors a << 16 | b
     float4 *qres = reinterpret_cast<float4 *>(wb + (size_t)a.tcap * 24 + CH * 4);  // vx, vy, vz, doca
     int *qpass = reinterpret_cast<int *>(wb + (size_t)a.tcap * 24 + CH * 20);
+    float2 *qst = reinterpret_cast<float2 *>(wb + (size_t)a.tcap * 24 + CH * 24);  // PCA offsets s, t
     const bool curved = (G.fp != 0.0);
+    const bool extras = a.m_pipi != nullptr;
     const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
     for (int iter = 0;; ++iter) {
@@ -990,10 +1052,11 @@ __global__ __launch_bounds__(BLOCK) void k_vertex(VertexArgs a, DevGeom G)
                 const float4 A = st[ia], B = st[ib];
                 const double g1 = -G.fp * (G.gc0 + G.gc1 * ((double)sq[ia] * 1e-3));
                 const double g2 = -G.fp * (G.gc0 + G.gc1 * ((double)sq[ib] * 1e-3));
-                double vx, vy, vz, dd;
-                const bool good = pca64(G, A.x, A.y, A.z, A.w, g1, B.x, B.y, B.z, B.w, g2, vx, vy, vz, dd);
+                double vx, vy, vz, dd, ps, pt;
+                const bool good = pca64(G, A.x, A.y, A.z, A.w, g1, B.x, B.y, B.z, B.w, g2, vx, vy, vz, dd, ps, pt);
                 qpass[q] = (good && (dd < G.doca_max)) ? 1 : 0;
                 qres[q] = make_float4((float)vx, (float)vy, (float)vz, (float)dd);
+                qst[q] = make_float2((float)ps, (float)pt);
             }
             wave_sync();
             // stage 3: order-preserving compaction of the passing pairs
@@ -1020,6 +1083,21 @@ __global__ __launch_bounds__(BLOCK) void k_vertex(VertexArgs a, DevGeom G)
                         a.vy[o] = R.y;
                         a.vz[o] = R.z;
                         a.vdoca[o] = R.w;
+                        if (extras) {
+                            const float4 TA = st[ia], TB = st[ib];
+                            const double g1 = -G.fp * (G.gc0 + G.gc1 * ((double)sq[ia] * 1e-3));
+                            const double g2 = -G.fp * (G.gc0 + G.gc1 * ((double)sq[ib] * 1e-3));
+                            const float2 ST = qst[q];
+                            float ex[6];
+                            vertex_extras(G, a.WL, TA, TB, g1, g2, a.sqop[a.seed_off[e] + (sslot[ia] >> 1)],
+                                          a.sqop[a.seed_off[e] + (sslot[ib] >> 1)], ST.x, ST.y, R, ex);
+                            a.m_pipi[o] = ex[0];
+                            a.m_ppi[o] = ex[1];
+                            a.line0[o] = ex[2];
+                            a.line1[o] = ex[3];
+                            a.line2[o] = ex[4];
+                            a.line3[o] = ex[5];
+                        }
                     }
                 }
             }

@@ -23,7 +23,7 @@ DS_F_BAD_OFFSETS, DS_F_CAPACITY, DS_F_NONFINITE = 1, 2, 4
 N_WEIGHTS = 1121
 
 EXPORTED = ("ds_create", "ds_destroy", "ds_load_geometry", "ds_find_tracks", "ds_ghost_kill", "ds_kill_clones",
-            "ds_candidate_slots", "ds_score_candidates", "ds_vertex", "ds_process", "ds_set_launch",
+            "ds_candidate_slots", "ds_score_candidates", "ds_load_lines", "ds_vertex", "ds_process", "ds_set_launch",
             "ds_get_launch", "ds_status_str")
 
 
@@ -76,6 +76,8 @@ class DsVertices(C.Structure):
         ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("doca", C.c_void_p),
         ("overflow", C.c_void_p),
         ("flags", C.c_void_p),
+        ("m_pipi", C.c_void_p), ("m_ppi", C.c_void_p),
+        ("line", C.c_void_p * 4),
     ]
 
 
@@ -109,6 +111,7 @@ def library() -> C.CDLL:
         lib.ds_ghost_kill.argtypes = [P, C.POINTER(DsEvents), C.POINTER(DsTracks), P]
         lib.ds_kill_clones.argtypes = [P, C.POINTER(DsEvents), C.POINTER(DsTracks), P]
         lib.ds_candidate_slots.argtypes = [P]
+        lib.ds_load_lines.argtypes = [P, C.POINTER(C.c_float), C.c_size_t]
         lib.ds_score_candidates.argtypes = [P, C.POINTER(DsEvents), C.POINTER(DsCandidates), P]
         lib.ds_vertex.argtypes = [P, C.POINTER(DsEvents), C.POINTER(DsTracks), C.c_float, C.POINTER(DsVertices),
                                   C.c_int, P]
@@ -231,10 +234,11 @@ class DeviceTracks:
 class DeviceVertices:
     """Vertex output for n_events events with cap_per_event slots each."""
 
-    def __init__(self, n_events: int, cap_per_event: int = 1024, device="cuda"):
+    def __init__(self, n_events: int, cap_per_event: int = 1024, device="cuda", extras: bool = False):
         import torch
         dev = torch.device(device)
         self.n_events, self.cap = int(n_events), int(cap_per_event)
+        self.extras = extras
         m = max(self.n_events * self.cap, 1)
         self.count = torch.zeros(max(self.n_events, 1), dtype=torch.int32, device=dev)
         self.i = torch.zeros(m, dtype=torch.int32, device=dev)
@@ -248,10 +252,20 @@ class DeviceVertices:
         s.count, s.i, s.j = _ptr(self.count), _ptr(self.i), _ptr(self.j)
         s.x, s.y, s.z, s.doca = _ptr(self.x), _ptr(self.y), _ptr(self.z), _ptr(self.doca)
         s.overflow, s.flags = _ptr(self.overflow), _ptr(self.flags)
+        if extras:
+            self.m_pipi = torch.zeros(m, dtype=torch.float32, device=dev)
+            self.m_ppi = torch.zeros(m, dtype=torch.float32, device=dev)
+            self.lines = torch.zeros((4, m), dtype=torch.float32, device=dev)
+            s.m_pipi, s.m_ppi = _ptr(self.m_pipi), _ptr(self.m_ppi)
+            for l in range(4):
+                s.line[l] = _ptr(self.lines[l])
         self.struct = s
 
     def to_numpy(self) -> Dict:
         out = {k: getattr(self, k).cpu().numpy() for k in ("i", "j", "x", "y", "z", "doca")}
+        if self.extras:
+            out["m_pipi"], out["m_ppi"] = self.m_pipi.cpu().numpy(), self.m_ppi.cpu().numpy()
+            out["lines"] = self.lines.cpu().numpy().T.copy()
         out["count"] = self.count[:self.n_events].cpu().numpy()
         out["overflow"] = int(self.overflow.item())
         out["flags"] = int(self.flags.item())
@@ -344,6 +358,11 @@ def ds_process(ctx, ev: DeviceEvents, trk: DeviceTracks, vtx: DeviceVertices, mo
                score_max: float = math.nan, stream=None) -> None:
     _check(library().ds_process(ctx, C.byref(ev.struct), C.byref(trk.struct), C.c_float(score_max),
                                 C.byref(vtx.struct), int(mode), _stream_handle(stream)), "ds_process")
+
+
+def ds_load_lines(ctx, weights) -> None:
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32))
+    _check(library().ds_load_lines(ctx, w.ctypes.data_as(C.POINTER(C.c_float)), w.size), "ds_load_lines")
 
 
 def ds_set_launch(ctx, kernel: int, block: int = 0, wg_per_cu: int = 0, bins: int = 0) -> None:

@@ -109,6 +109,14 @@ def mlp_weights(seed: int = 0, scale: float = 0.3) -> np.ndarray:
     return np.random.default_rng(seed).normal(0.0, scale, N_MLP_WEIGHTS).astype(np.float32)
 
 
+N_LINE_WEIGHTS = 4 * (32 * 12 + 32 + 32 + 1)  # four 12 -> 32 -> 1 trigger-line networks
+
+
+def line_weights(seed: int = 1, scale: float = 0.3) -> np.ndarray:
+    """Trigger-line networks, each W1[32][12], b1[32], W2[1][32], b2[1], all N(0, scale)."""
+    return np.random.default_rng(seed).normal(0.0, scale, N_LINE_WEIGHTS).astype(np.float32)
+
+
 @dataclasses.dataclass
 class EventBatch:
     """SoA batch.  Offsets are event-major; ``hit_off`` is (event, layer)."""

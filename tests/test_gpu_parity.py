@@ -380,3 +380,55 @@ def test_every_candidate_scored_matches_oracle():
     finally:
         torch.cuda.synchronize()
         c.close()
+
+
+def test_vertex_masses_and_trigger_lines_match_oracle(ctx):
+    wl = synth.line_weights()
+    s = synth.vertex_track_sample(n_events=30, n_pairs=6, n_random=30, seed=41)
+    n = len(s["x"])
+    E = len(s["seed_off"]) - 1
+    b = synth.EventBatch(E, s["seed_off"], s["x"], s["y"], s["tx"], s["ty"], s["sqop"],
+                         np.zeros(4 * E + 1, np.int32), np.zeros(0, np.float32))
+    ev = ds.DeviceEvents(b)
+    tr = ds.DeviceTracks(n)
+    for k in ("x", "y", "tx", "ty", "qop", "score"):
+        getattr(tr, k).copy_(torch.from_numpy(s[k]))
+    tr.nhits.copy_(torch.from_numpy(s["nhits"]))
+    vt = ds.DeviceVertices(E, 256, extras=True)
+    with pytest.raises(ds.DsError):          # lines not loaded yet
+        ds.ds_vertex(ctx.handle, ev, tr, math.inf, vt, ds.DS_MODE_PERSISTENT)
+    ds.ds_load_lines(ctx.handle, wl)
+    for fp in (0.0, 1.0):
+        g = dict(G0, fringe_polarity=fp)
+        c = ds.Context(0, g, W) if fp else ctx
+        try:
+            if fp:
+                ds.ds_load_lines(c.handle, wl)
+            vt = ds.DeviceVertices(E, 256, extras=True)
+            ds.ds_vertex(c.handle, ev, tr, math.inf, vt, ds.DS_MODE_PERSISTENT)
+            torch.cuda.synchronize()
+            gv = vt.to_numpy()
+            st = dict(x=s["x"], y=s["y"], tx=s["tx"], ty=s["ty"], qop=s["qop"], nhits=s["nhits"])
+            rv = O.vertex(s["seed_off"], s["sqop"], st, s["score"].astype(np.float64), g, math.inf, 256,
+                          line_weights=wl.astype(np.float64))
+            parity.compare_vertices(gv, rv, g["doca_max"])
+            G_ = parity.vertex_dict(gv)
+            nchk = 0
+            for e in range(E):
+                for m in range(int(rv["count"][e])):
+                    k = e * 256 + m
+                    key = (e, int(rv["i"][k]), int(rv["j"][k]))
+                    if key not in G_:
+                        continue
+                    mg = [mm for mm in range(int(gv["count"][e])) if (gv["i"][e * 256 + mm], gv["j"][e * 256 + mm]) == key[1:]][0]
+                    kg = e * 256 + mg
+                    assert abs(gv["m_pipi"][kg] - rv["m_pipi"][k]) <= 1e-4 * rv["m_pipi"][k] + 1e-3
+                    assert abs(gv["m_ppi"][kg] - rv["m_ppi"][k]) <= 1e-4 * rv["m_ppi"][k] + 1e-3
+                    assert np.max(np.abs(gv["lines"][kg] - rv["lines"][k])) <= 1e-5
+                    nchk += 1
+            say(f"[parity] masses and lines fp={fp}: {nchk} vertices checked")
+            assert nchk > E
+        finally:
+            if fp:
+                torch.cuda.synchronize()
+                c.close()

@@ -541,3 +541,75 @@ def test_candidate_rows_are_the_valid_candidates_and_include_the_track():
                     assert rows["score"][k] == res["score"][i]
                 k += 1
     assert k == len(rows["seed"]) and k > 1000
+
+
+# -------------------------------------------- mass and trigger lines -----
+
+def _two_body(M, m1, m2, P, theta, phi, axis_t):
+    """Lab momenta of a two-body decay: parent of mass M (GeV) and momentum P
+    along (tx, ty, 1); daughter 1 at (theta, phi) in the parent frame."""
+    pst = math.sqrt((M * M - (m1 + m2) ** 2) * (M * M - (m1 - m2) ** 2)) / (2 * M)
+    n = np.array([math.sin(theta) * math.cos(phi), math.sin(theta) * math.sin(phi), math.cos(theta)])
+    e1, e2 = math.sqrt(pst ** 2 + m1 ** 2), math.sqrt(pst ** 2 + m2 ** 2)
+    E = math.sqrt(P * P + M * M)
+    beta, gam = P / E, E / M
+    z = np.array([axis_t[0], axis_t[1], 1.0])
+    z /= np.linalg.norm(z)
+    out = []
+    for e, pv in ((e1, pst * n), (e2, -pst * n)):
+        # boost along the parent direction z: build an orthonormal frame with z
+        x = np.cross([0.0, 1.0, 0.0], z)
+        x /= np.linalg.norm(x)
+        y = np.cross(z, x)
+        pl = gam * (pv[2] + beta * e)
+        out.append(pv[0] * x + pv[1] * y + pl * z)
+    return out
+
+
+def test_invariant_mass_of_constructed_decays():
+    g = geom(fringe_polarity=0.0)
+    zr = g["z_ref"]
+    wl = np.zeros(synth.N_LINE_WEIGHTS)
+    rng = np.random.default_rng(3)
+    for M, m1, m2, col in ((0.497611, 0.13957039, 0.13957039, 0), (1.115683, 0.93827209, 0.13957039, 1)):
+        for _ in range(20):
+            V = np.array([rng.uniform(-100, 100), rng.uniform(-100, 100), rng.uniform(200, 2000)])
+            P = rng.uniform(5, 60)
+            p1, p2 = _two_body(M, m1, m2, P, rng.uniform(0.3, 2.8), rng.uniform(0, 6.28),
+                               (rng.uniform(-0.1, 0.1), rng.uniform(-0.1, 0.1)))
+            if col == 1 and np.linalg.norm(p1) <= np.linalg.norm(p2):
+                continue  # the Lambda hypothesis takes the faster track as the proton
+            trs = []
+            for p in (p1, p2):
+                tx, ty = p[0] / p[2], p[1] / p[2]
+                trs.append([V[0] + tx * (zr - V[2]), V[1] + ty * (zr - V[2]), tx, ty, 0.0])
+            out = O.vertex_extras(g, trs[0], trs[1], 1.0 / np.linalg.norm(p1), -1.0 / np.linalg.norm(p2), V[2], V[2],
+                                  [V[0], V[1], V[2], 0.0], wl)
+            assert out[col] == pytest.approx(1000.0 * M, rel=1e-9)
+            assert np.all(out[2:] == 0.5)   # zero weights: every line gives sigmoid(0)
+
+
+def test_trigger_line_network_inputs_and_structure():
+    """One-hot networks read single inputs back: line l with W1[0][k] = 1 and
+    W2[0] = 1 outputs sigmoid(relu(f_k))."""
+    g = geom(fringe_polarity=0.0)
+    nw = 32 * 12 + 32 + 32 + 1
+    V = [30.0, 40.0, 1500.0, 0.25]
+    t1 = [1.0, 2.0, 0.1, 0.05, 0.0]
+    t2 = [3.0, 1.0, -0.05, 0.02, 0.0]
+    q1, q2 = 1.0 / 12.5, -1.0 / 3.0
+    expect = {0: math.log(12.5), 1: math.log(3.0), 2: 0.1 / 0.3, 3: 0.05 / 0.3, 6: 1.5, 7: 0.5, 8: 0.25}
+    for k, val in expect.items():
+        wl = np.zeros(4 * nw)
+        for l in range(4):
+            base = l * nw
+            wl[base + 0 * 12 + k] = 1.0          # W1[0][k]
+            wl[base + 32 * 12 + 32 + 0] = 1.0   # W2[0][0]
+        out = O.vertex_extras(g, t1, t2, q1, q2, 1500.0, 1500.0, V, wl)
+        assert np.allclose(out[2:], 1.0 / (1.0 + math.exp(-max(val, 0.0))), atol=1e-12), k
+    # biases: W2 = 0, b2 = l - 1.5 gives sigmoid(b2) for line l
+    wl = np.zeros(4 * nw)
+    for l in range(4):
+        wl[l * nw + nw - 1] = l - 1.5
+    out = O.vertex_extras(g, t1, t2, q1, q2, 1500.0, 1500.0, V, wl)
+    assert np.allclose(out[2:], [1.0 / (1.0 + math.exp(-(l - 1.5))) for l in range(4)], atol=1e-15)
