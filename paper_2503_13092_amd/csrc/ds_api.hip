@@ -707,7 +707,11 @@ ds_status ds_score_candidates(ds_ctx *c, const ds_events *ev, const ds_candidate
         hipLaunchKernelGGL(ds::k_clear_rows, dim3(grid), dim3(256), 0, s, out->nhits, rows);
         if (hipGetLastError() != hipSuccess) return DS_E_DEVICE;
     }
-    return dev_err(run_track(c, p, DS_MODE_PERSISTENT, s));
+    hipError_t e = run_track(c, p, DS_MODE_PERSISTENT, s);
+    if (e != hipSuccess) return DS_E_DEVICE;
+    const int grid = std::max(1, std::min(ev->n_events, c->n_cu * 8));
+    hipLaunchKernelGGL(ds::k_score_rows, dim3(grid), dim3(256), 0, s, p.a, c->G);
+    return dev_err(hipGetLastError());
 }
 
 ds_status ds_vertex(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, float score_max, const ds_vertices *out,

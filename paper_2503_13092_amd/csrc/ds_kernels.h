@@ -121,6 +121,15 @@ struct VertexArgs {
 
 // ----------------------------------------------------------------- helpers
 
+// Workgroup barrier ordering LDS traffic only: unlike __syncthreads it does not
+// wait for the wave's outstanding global stores.
+__device__ inline void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 template <int BLOCK>
 __device__ inline int block_exclusive_scan(int v, int *s_wsum, int *total)
 {
@@ -132,7 +141,7 @@ __device__ inline int block_exclusive_scan(int v, int *s_wsum, int *total)
         if (lane >= d) x += y;
     }
     if (lane == 63) s_wsum[wid] = x;
-    __syncthreads();
+    lds_barrier();
     int off = 0, tot = 0;
 #pragma unroll
     for (int w = 0; w < BLOCK / 64; ++w) {
@@ -140,7 +149,7 @@ __device__ inline int block_exclusive_scan(int v, int *s_wsum, int *total)
         off += (w < wid) ? s : 0;
         tot += s;
     }
-    __syncthreads();
+    lds_barrier();
     *total = tot;
     return off + x - v;
 }
@@ -161,6 +170,16 @@ __device__ inline bool finite5(float a, float b, float c, float d, float e)
 __device__ inline bool key_less(double da, float ua, int ia, double db, float ub, int ib)
 {
     return da < db || (da == db && (ua < ub || (ua == ub && ia < ib)));
+}
+
+// Window order of the hit at LDS position p (distance d, coordinate u) against
+// the kept hit at position pk (distance dk; pk < 0: empty slot).
+__device__ inline bool before(const float *hu_s, const uint16_t *hidx_s, double d, float u, int p, double dk, int pk)
+{
+    if (d != dk || pk < 0) return d < dk || pk < 0;
+    const float uk = hu_s[pk];
+    if (u != uk) return u < uk;
+    return hidx_s[p] < hidx_s[pk];
 }
 
 // LDS positions [p_lo, p_hi) of the buckets of `layer` covering [m - W, m + W]
@@ -184,8 +203,9 @@ __device__ inline unsigned long long pack_key(int n, double chi2, int c)
 }
 
 struct SeedConst {
-    double c[4];   // c_L = x_S(z_L) - y(z_L) tan(alpha_L)
-    double w2;     // refined window half-width
+    double c[4];     // c_L = x_S(z_L) - y(z_L) tan(alpha_L)
+    float q;         // seed q/p (window widths and the kinked prediction)
+    uint16_t lo, hi; // LDS range of the UTbX buckets covering the first window
 };
 
 // Least squares of residuals rho_L over a valid layer set (mask 11, 13, 14 or 15).
@@ -327,9 +347,8 @@ __device__ inline bool seed_frame(const DevGeom &G, float fsx, float fsy, float 
         const double yl = fma(sty, dzs, sy);
         sc.c[L] = fma(-yl, G.tana[L], xs);
     }
-    const double aq = fabs(sq);
-    W1 = fma(G.w1c1, aq, G.w1c0);
-    sc.w2 = fma(G.w2c1, aq, G.w2c0);
+    sc.q = fsq;
+    W1 = fma(G.w1c1, fabs(sq), G.w1c0);
     m3 = sc.c[3] + G.mk * sq * (G.zm - G.zl[3]);
     return true;
 }
@@ -342,31 +361,48 @@ __device__ inline void item_candidates(const DevGeom &G, const TrackArgs &a, con
                                        const uint16_t *hidx_s, const int *E, const SeedConst &sc, int r3, int p3,
                                        Visit &&visit)
 {
+    const double W2 = fma(G.w2c1, fabs((double)sc.q), G.w2c0);
     const double rho3 = (double)hu_s[p3] - sc.c[3];
+    double m[3];
+    int lo[3], len[3];
+    int maxlen = 0;
+#pragma unroll
+    for (int L = 0; L < 3; ++L) {
+        m[L] = fma(rho3, G.ffac[L], sc.c[L]);
+        int hi;
+        bin_range(E, L, a.nb, a.u0, a.inv_bw, m[L], W2, lo[L], hi);
+        len[L] = hi - lo[L];
+        maxlen = max(maxlen, len[L]);
+    }
+    // the three layers advance together: one LDS round trip per step; the two
+    // best keep (|delta|, position), u and index are re-read only on ties
+    double d0[3] = {INFINITY, INFINITY, INFINITY}, d1[3] = {INFINITY, INFINITY, INFINITY};
+    int p0k[3] = {-1, -1, -1}, p1k[3] = {-1, -1, -1};
+    for (int k = 0; k < maxlen; ++k) {
+#pragma unroll
+        for (int L = 0; L < 3; ++L) {
+            if (k >= len[L]) continue;
+            const int p = lo[L] + k;
+            const float u = hu_s[p];
+            const double d = fabs((double)u - m[L]);
+            if (!(d <= W2)) continue;
+            if (before(hu_s, hidx_s, d, u, p, d0[L], p0k[L])) {
+                d1[L] = d0[L];
+                p1k[L] = p0k[L];
+                d0[L] = d;
+                p0k[L] = p;
+            } else if (before(hu_s, hidx_s, d, u, p, d1[L], p1k[L])) {
+                d1[L] = d;
+                p1k[L] = p;
+            }
+        }
+    }
     int A[3][MAX_CLOSEST];
     int nA[3];
 #pragma unroll
     for (int L = 0; L < 3; ++L) {
-        const double m = fma(rho3, G.ffac[L], sc.c[L]);
-        int lo, hi;
-        bin_range(E, L, a.nb, a.u0, a.inv_bw, m, sc.w2, lo, hi);
-        double d0 = INFINITY, d1 = INFINITY;
-        float u0k = 0.0f, u1k = 0.0f;
-        int i0k = 0, i1k = 0, p0k = -1, p1k = -1;
-        for (int p = lo; p < hi; ++p) {
-            const float u = hu_s[p];
-            const double d = fabs((double)u - m);
-            if (!(d <= sc.w2)) continue;
-            const int id = hidx_s[p];
-            if (key_less(d, u, id, d0, u0k, i0k)) {
-                d1 = d0; u1k = u0k; i1k = i0k; p1k = p0k;
-                d0 = d; u0k = u; i0k = id; p0k = p;
-            } else if (key_less(d, u, id, d1, u1k, i1k)) {
-                d1 = d; u1k = u; i1k = id; p1k = p;
-            }
-        }
-        A[L][0] = G.ncl[L] >= 1 ? p0k : -1;
-        A[L][1] = G.ncl[L] >= 2 ? p1k : -1;
+        A[L][0] = G.ncl[L] >= 1 ? p0k[L] : -1;
+        A[L][1] = G.ncl[L] >= 2 ? p1k[L] : -1;
         nA[L] = (A[L][0] >= 0 ? 1 : 0) + (A[L][1] >= 0 ? 1 : 0);
     }
     double rho[4];
@@ -396,6 +432,27 @@ __device__ inline void item_candidates(const DevGeom &G, const TrackArgs &a, con
             }
         }
     }
+}
+
+// Rank of the UTbX hit at p3 among the seed's first-window hits (by the
+// window key), or -1 if it is outside the window.
+__device__ inline int first_window_rank(const DevGeom &G, const float *hu_s, const uint16_t *hidx_s,
+                                        const SeedConst &sc, int p3)
+{
+    const double q = sc.q;
+    const double W1 = fma(G.w1c1, fabs(q), G.w1c0);
+    const double m3 = sc.c[3] + G.mk * q * (G.zm - G.zl[3]);
+    const float u3 = hu_s[p3];
+    const double d3 = fabs((double)u3 - m3);
+    if (!(d3 <= W1)) return -1;
+    const int i3 = hidx_s[p3];
+    int rank = 0;
+    for (int p = sc.lo; p < sc.hi; ++p) {
+        const float u = hu_s[p];
+        const double d = fabs((double)u - m3);
+        if (d < d3 || (d == d3 && p != p3 && key_less(d, u, (int)hidx_s[p], d3, u3, i3))) ++rank;
+    }
+    return rank;
 }
 
 // Best candidate through one UTbX hit: more hits, then lower chi2, then lower index.
@@ -483,7 +540,7 @@ __device__ inline void write_candidate_row(const TrackArgs &a, const DevGeom &G,
                                            double be, double c2, const float *hu_s, const uint16_t *hidx_s,
                                            const int bp[4])
 {
-    const StoredTrack t = stored_track(a, G, i, n, al, be, c2, hu_s, bp, true);
+    const StoredTrack t = stored_track(a, G, i, n, al, be, c2, hu_s, bp, false);
     const size_t r = (size_t)i * (size_t)a.cmax + (size_t)c;
     a.r_seed[r] = i;
     a.r_cand[r] = c;
@@ -498,7 +555,6 @@ __device__ inline void write_candidate_row(const TrackArgs &a, const DevGeom &G,
     a.r_ty[r] = t.ty;
     a.r_qop[r] = t.qop;
     a.r_chi2[r] = t.chi2;
-    a.r_score[r] = t.score;
 }
 
 // Stage one event's hits into LDS, bucketed by (layer, bin); the order inside a
@@ -515,7 +571,7 @@ __device__ inline bool stage_hits(const TrackArgs &a, int hb, const int hl[4], i
     const int NBT = 4 * a.nb;
     for (int k = tid; k <= NBT; k += BLOCK) E[k] = 0;
     if (tid == 0) *s_bad = 0;
-    __syncthreads();
+    lds_barrier();
     const int rounds = (nh + HPT * BLOCK - 1) / (HPT * BLOCK);
     float u[HPT];
     for (int r = 0; r < rounds; ++r) {
@@ -540,7 +596,7 @@ __device__ inline bool stage_hits(const TrackArgs &a, int hb, const int hl[4], i
         }
         if (bad) *s_bad = 1;
     }
-    __syncthreads();
+    lds_barrier();
     if (*s_bad) return false;
     // exclusive scan of the bucket counts held at E[1..NBT]: E[b + 1] = start of bucket b
     const int per = NBT / BLOCK;
@@ -553,7 +609,7 @@ __device__ inline bool stage_hits(const TrackArgs &a, int hb, const int hl[4], i
         E[1 + tid * per + j] = run;
         run += cnt;
     }
-    __syncthreads();
+    lds_barrier();
     // placing pass: E[b + 1] advances to the end of bucket b = start of bucket b + 1
     for (int r = 0; r < rounds; ++r) {
         const int k0 = r * HPT * BLOCK + tid;
@@ -575,7 +631,7 @@ __device__ inline bool stage_hits(const TrackArgs &a, int hb, const int hl[4], i
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
     return true;
 }
 
@@ -613,7 +669,7 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
                 e = atomicAdd(&a.counter[0], 1);
             s_ev = e;
         }
-        __syncthreads();
+        lds_barrier();
         const int e = s_ev;
         if (e >= a.n_events) break;
 
@@ -633,11 +689,11 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
             if (tid == 0) atomicOr(a.flags, bad);
             if (seeds_ok)
                 for (int i = s0 + tid; i < s1; i += BLOCK) write_empty_track(a, i);
-            __syncthreads();
+            lds_barrier();
             continue;
         }
         if (s1 == s0) {
-            __syncthreads();
+            lds_barrier();
             continue;
         }
         int hl[4];
@@ -646,7 +702,7 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
         if (!stage_hits<BLOCK>(a, ho[0], hl, nh, hu_s, hidx_s, E, &s_bad, s_wsum)) {
             if (tid == 0) atomicOr(a.flags, F_NONFINITE);
             for (int i = s0 + tid; i < s1; i += BLOCK) write_empty_track(a, i);
-            __syncthreads();
+            lds_barrier();
             continue;
         }
 
@@ -656,52 +712,50 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
                 s_nacc = min(BLOCK, s1 - sc0);
                 s_nitems = 0;
             }
-            // phase A: lane per seed, first window in UTbX, ranks of its hits
+            // phase A: lane per seed, the UTbX bucket range of its first window;
+            // every hit of the range becomes an item (seed, hit)
             const int i = sc0 + tid;
             const bool have = i < s1;
             SeedConst sc;
             double m3 = 0.0, W1 = 0.0;
-            int n3 = 0, p_lo = 0, p_hi = 0;
+            int n_rng = 0, p_lo = 0, p_hi = 0;
             if (have) {
                 if (seed_frame(G, a.sx[i], a.sy[i], a.stx[i], a.sty[i], a.sqop[i], sc, m3, W1)) {
-                    bin_range(E, 3, a.nb, a.u0, a.inv_bw, m3, W1, p_lo, p_hi);
-                    int n_in = 0;
-                    for (int p = p_lo; p < p_hi; ++p) n_in += (fabs((double)hu_s[p] - m3) <= W1) ? 1 : 0;
-                    n3 = min(n_in, G.max_l3);
+                    if (G.max_l3 > 0) bin_range(E, 3, a.nb, a.u0, a.inv_bw, m3, W1, p_lo, p_hi);
+                    n_rng = p_hi - p_lo;
                 } else {
                     atomicOr(a.flags, F_NONFINITE);
                 }
             }
+            sc.lo = (uint16_t)p_lo;
+            sc.hi = (uint16_t)p_hi;
             int tot;
-            const int excl = block_exclusive_scan<BLOCK>(n3, s_wsum, &tot);
-            const bool acc = have && (excl + n3 <= a.icap);
+            const int excl = block_exclusive_scan<BLOCK>(n_rng, s_wsum, &tot);
+            bool acc = have && (excl + n_rng <= a.icap);
+            if (tid == 0 && have && !acc) {
+                // one seed alone overflows the item buffer: truncate its range (flagged)
+                atomicOr(a.flags, F_CAPACITY);
+                n_rng = a.icap;
+                sc.hi = (uint16_t)(p_lo + n_rng);
+                acc = true;
+            }
             if (have && !acc) atomicMin(&s_nacc, tid);
             if (acc) {
                 s_c[tid] = sc;
                 s_key[tid] = ~0ull;
                 s_base[tid] = excl;
-                atomicMax(&s_nitems, excl + n3);
-                for (int p = p_lo; p < p_hi && n3 > 0; ++p) {
-                    const float up = hu_s[p];
-                    const double dp = fabs((double)up - m3);
-                    if (!(dp <= W1)) continue;
-                    const int ip = hidx_s[p];
-                    int rank = 0;
-                    for (int q = p_lo; q < p_hi; ++q) {
-                        const float uq = hu_s[q];
-                        const double dq = fabs((double)uq - m3);
-                        if (dq <= W1 && key_less(dq, uq, (int)hidx_s[q], dp, up, ip)) ++rank;
-                    }
-                    if (rank < n3) it_desc[excl + rank] = ((uint32_t)tid << 20) | ((uint32_t)rank << 16) | (uint32_t)p;
-                }
+                atomicMax(&s_nitems, excl + n_rng);
+                for (int k = 0; k < n_rng; ++k) it_desc[excl + k] = ((uint32_t)tid << 16) | (uint32_t)(p_lo + k);
             }
-            __syncthreads();
+            lds_barrier();
             const int nacc = s_nacc, n_items = s_nitems;
             // phase B: lane per (seed, UTbX hit) item
             for (int it = tid; it < n_items; it += BLOCK) {
                 const uint32_t d = it_desc[it];
-                const int sl = (int)(d >> 20), r3 = (int)((d >> 16) & 15u), p3 = (int)(d & 0xffffu);
+                const int sl = (int)(d >> 16), p3 = (int)(d & 0xffffu);
                 const SeedConst scs = s_c[sl];
+                const int r3 = first_window_rank(G, hu_s, hidx_s, scs, p3);
+                if (r3 < 0 || r3 >= G.max_l3) continue;
                 if (CANDS) {
                     item_candidates(G, a, hu_s, hidx_s, E, scs, r3, p3,
                                     [&](int n, int c, double al, double be, double c2, const int bp[4]) {
@@ -712,17 +766,16 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
                 int bn, bc, bp[4] = {-1, -1, -1, -1};
                 double bchi2;
                 item_best(G, a, hu_s, hidx_s, E, scs, r3, p3, bn, bchi2, bc, bp);
-                unsigned long long packed = ~0ull;
                 if (bn > 0) {
-                    atomicMin(&s_key[sl], pack_key(bn, bchi2, bc));
-                    packed = 0;
+                    unsigned long long packed = 0;
 #pragma unroll
                     for (int L = 0; L < 4; ++L)
                         packed |= (unsigned long long)(bp[L] >= 0 ? (unsigned)bp[L] : 0xffffu) << (16 * L);
+                    it_hits[s_base[sl] + r3] = packed;
+                    atomicMin(&s_key[sl], pack_key(bn, bchi2, bc));
                 }
-                it_hits[it] = packed;
             }
-            __syncthreads();
+            lds_barrier();
             // phase C: lane per seed, write the winner (and its ghost score)
             if (!CANDS && tid < nacc) {
                 const unsigned long long key = s_key[tid];
@@ -740,7 +793,7 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
                     write_track(a, G, i, s_c[tid], hu_s, hidx_s, bp, c);
                 }
             }
-            __syncthreads();
+            lds_barrier();
             sc0 += nacc;
         }
     }
@@ -760,6 +813,42 @@ __global__ void k_clear_rows(int *r_nhits, long long n)
 {
     for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
         r_nhits[k] = 0;
+}
+
+// Ghost scores of the candidate rows: one workgroup per event, lane per row.
+__global__ __launch_bounds__(256) void k_score_rows(TrackArgs a, DevGeom G)
+{
+    for (int e = blockIdx.x; e < a.n_events; e += gridDim.x) {
+        const int s0 = a.seed_off[e], s1 = a.seed_off[e + 1];
+        int ho[5];
+#pragma unroll
+        for (int L = 0; L < 5; ++L) ho[L] = a.hit_off[4 * e + L];
+        bool ok = (0 <= s0) && (s0 <= s1) && (s1 <= a.n_seeds) && (0 <= ho[0]) && (ho[4] <= a.n_hits);
+#pragma unroll
+        for (int L = 0; L < 4; ++L) ok = ok && (ho[L] <= ho[L + 1]);
+        if (!ok) continue;
+        const long long r0 = (long long)s0 * a.cmax, r1 = (long long)s1 * a.cmax;
+        for (long long r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+            const int nh = a.r_nhits[r];
+            if (nh <= 0) continue;
+            const int i = (int)(r / a.cmax);
+            const int hh[4] = {a.r_h0[r], a.r_h1[r], a.r_h2[r], a.r_h3[r]};
+            float hu4[4];
+            int has = 0;
+#pragma unroll
+            for (int L = 0; L < 4; ++L) {
+                hu4[L] = 0.0f;
+                if (hh[L] >= 0 && hh[L] < ho[L + 1] - ho[L]) {
+                    hu4[L] = a.hu[ho[L] + hh[L]];
+                    has |= 1 << L;
+                }
+            }
+            float f[NF];
+            ghost_features(G, a.r_x[r], a.r_y[r], a.r_tx[r], a.r_ty[r], a.r_qop[r], a.r_chi2[r], nh, a.sx[i], a.sy[i],
+                           a.stx[i], a.sty[i], a.sqop[i], hu4, has, f);
+            a.r_score[r] = mlp_score(a.W, f);
+        }
+    }
 }
 
 // Standalone ghost-killer: one workgroup per event (grid-stride), lane per seed.
@@ -992,20 +1081,40 @@ __global__ __launch_bounds__(BLOCK) void k_vertex(VertexArgs a, DevGeom G)
             }
             continue;
         }
-        // kept tracks, compacted in slot order
+        // kept tracks, compacted in slot order; four rounds of 64 seeds share
+        // one round trip for the selection and one for the states
         int n = 0;
-        for (int base = s0; base < s1; base += 64) {
-            const int i = base + lane;
-            bool kept = false;
-            if (i < s1) kept = (a.nhits[i] > 0) && (a.score[i] < a.score_max);
-            const unsigned long long m = __ballot(kept);
-            if (kept) {
-                const int k = n + __popcll(m & lt_mask);
-                st[k] = make_float4(a.x[i], a.y[i], a.tx[i], a.ty[i]);
-                sq[k] = a.qop[i];
-                sslot[k] = ((i - s0) << 1) | (a.sqop[i] > 0.0f ? 1 : 0);
+        constexpr int R = 4;
+        for (int base = s0; base < s1; base += 64 * R) {
+            bool kept[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = base + 64 * r + lane;
+                kept[r] = (i < s1) && (a.nhits[i] > 0) && (a.score[i] < a.score_max);
             }
-            n += __popcll(m);
+            float4 v[R];
+            float qv[R];
+            int pos[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = base + 64 * r + lane;
+                if (kept[r]) {
+                    v[r] = make_float4(a.x[i], a.y[i], a.tx[i], a.ty[i]);
+                    qv[r] = a.qop[i];
+                    pos[r] = a.sqop[i] > 0.0f ? 1 : 0;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const unsigned long long m = __ballot(kept[r]);
+                if (kept[r]) {
+                    const int k = n + __popcll(m & lt_mask);
+                    st[k] = v[r];
+                    sq[k] = qv[r];
+                    sslot[k] = ((base + 64 * r + lane - s0) << 1) | pos[r];
+                }
+                n += __popcll(m);
+            }
         }
         wave_sync();
         const int npairs = n * (n - 1) / 2;
