@@ -63,7 +63,7 @@ ds_status dev_err(hipError_t e) { return e == hipSuccess ? DS_OK : DS_E_DEVICE; 
 
 size_t round16(size_t v) { return (v + 15) & ~size_t(15); }
 
-size_t track_lds(int hcap, int nb, int block, int icap)
+size_t track_lds(int hcap, int nb, int block, int icap, int tcap)
 {
     size_t off = (size_t)hcap * 4;
     off = round16(off + (size_t)hcap * 2);
@@ -72,7 +72,7 @@ size_t track_lds(int hcap, int nb, int block, int icap)
     off += (size_t)block * 8;
     off = round16(off + (size_t)block * 4);
     off = round16(off + (size_t)icap * 4);
-    return off + (size_t)icap * 8;
+    return off + (size_t)icap * 8 + (size_t)tcap * 24;
 }
 
 size_t vertex_lds(int tcap, int block) { return ((size_t)tcap * 24 + (size_t)64 * VTX_PPT * 32) * (size_t)(block / 64); }
@@ -138,9 +138,11 @@ template <int B>
 hipError_t launch_track_b(const ds::TrackArgs &a, const ds::DevGeom &G, int grid, size_t lds, hipStream_t s)
 {
     if (a.cmax > 0)
-        hipLaunchKernelGGL((ds::k_track<B, true>), dim3(grid), dim3(B), lds, s, a, G);
+        hipLaunchKernelGGL((ds::k_track<B, true, false>), dim3(grid), dim3(B), lds, s, a, G);
+    else if (a.vcount)
+        hipLaunchKernelGGL((ds::k_track<B, false, true>), dim3(grid), dim3(B), lds, s, a, G);
     else
-        hipLaunchKernelGGL((ds::k_track<B, false>), dim3(grid), dim3(B), lds, s, a, G);
+        hipLaunchKernelGGL((ds::k_track<B, false, false>), dim3(grid), dim3(B), lds, s, a, G);
     return hipGetLastError();
 }
 
@@ -177,14 +179,12 @@ hipError_t launch_vertex(int block, const ds::VertexArgs &a, const ds::DevGeom &
 hipError_t set_kernel_attributes()
 {
     const void *fns[] = {
-        reinterpret_cast<const void *>(&ds::k_track<64, false>),
-        reinterpret_cast<const void *>(&ds::k_track<128, false>),
-        reinterpret_cast<const void *>(&ds::k_track<256, false>),
-        reinterpret_cast<const void *>(&ds::k_track<512, false>),
-        reinterpret_cast<const void *>(&ds::k_track<64, true>),
-        reinterpret_cast<const void *>(&ds::k_track<128, true>),
-        reinterpret_cast<const void *>(&ds::k_track<256, true>),
-        reinterpret_cast<const void *>(&ds::k_track<512, true>),
+#define DS_TRACK_FNS(B)                                                                                     \
+    reinterpret_cast<const void *>(&ds::k_track<B, false, false>),                                          \
+        reinterpret_cast<const void *>(&ds::k_track<B, true, false>),                                       \
+        reinterpret_cast<const void *>(&ds::k_track<B, false, true>)
+        DS_TRACK_FNS(64), DS_TRACK_FNS(128), DS_TRACK_FNS(256), DS_TRACK_FNS(512),
+#undef DS_TRACK_FNS
         reinterpret_cast<const void *>(&ds::k_vertex<64, VTX_PPT>),
         reinterpret_cast<const void *>(&ds::k_vertex<128, VTX_PPT>),
         reinterpret_cast<const void *>(&ds::k_vertex<256, VTX_PPT>),
@@ -210,14 +210,17 @@ struct VertexPlan {
     size_t lds;
 };
 
-ds_status plan_track(ds_ctx *c, const ds_events *ev, const ds_tracks *out, int fuse, int *counters, TrackPlan *p)
+ds_status plan_track(ds_ctx *c, const ds_events *ev, const ds_tracks *out, int fuse, int *counters, TrackPlan *p,
+                     bool vertex_fused = false)
 {
     const int nb = c->trk.bins;
     int hcap = round_up(std::max(ev->max_hits_per_event, 1), 64);
     const int block = c->trk.block;
     // items per chunk: room for ITEMS_PER_SEED per seed; a chunk shrinks when its seeds need more
     const int icap = std::max(block * ITEMS_PER_SEED, ds::MAX_L3);
-    size_t lds = track_lds(hcap, nb, block, icap);
+    const int tcap = vertex_fused ? round_up(std::max(ev->max_seeds_per_event, 1), 64) : 0;
+    if (tcap > 65535) return DS_E_CAPACITY;
+    size_t lds = track_lds(hcap, nb, block, icap, tcap);
     if (lds > LDS_LIMIT) return DS_E_CAPACITY;
     ds::TrackArgs &a = p->a;
     std::memset(&a, 0, sizeof(a));
@@ -254,6 +257,7 @@ ds_status plan_track(ds_ctx *c, const ds_events *ev, const ds_tracks *out, int f
     a.ev_single = -1;
     a.hcap = hcap;
     a.icap = icap;
+    a.tcap = tcap;
     a.nb = nb;
     a.u0 = (float)c->u_min;
     a.inv_bw = (float)((double)nb / (c->u_max - c->u_min));
@@ -781,6 +785,33 @@ ds_status ds_process(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, float
     if (ck) {
         st = clone_args(ev, trk, &ca, &clds);
         if (st != DS_OK) return st;
+    }
+    if (!ck && mode != DS_MODE_PER_EVENT) {
+        // one launch: tracking, ghost-killer and vertexing fused per event
+        TrackPlan fp;
+        st = plan_track(c, ev, trk, 1, counters, &fp, true);
+        if (st != DS_OK) return st;
+        ds::TrackArgs &a = fp.a;
+        a.score_max = score_max;
+        a.vcap = out->cap_per_event;
+        a.vcount = out->count;
+        a.vi = out->i;
+        a.vj = out->j;
+        a.vx = out->x;
+        a.vy = out->y;
+        a.vz = out->z;
+        a.vdoca = out->doca;
+        a.voverflow = out->overflow;
+        a.vflags = out->flags;
+        a.m_pipi = out->m_pipi;
+        a.m_ppi = out->m_ppi;
+        a.line0 = out->line[0];
+        a.line1 = out->line[1];
+        a.line2 = out->line[2];
+        a.line3 = out->line[3];
+        a.WL = c->d_WL;
+        std::string fkey = graph_key(5, &a, sizeof(a), fp.block, fp.grid, fp.lds);
+        return run_maybe_graph(c, mode, fkey, s, [&](hipStream_t ss) { return run_track(c, fp, mode, ss); });
     }
     std::string key = graph_key(ck ? 4 : 2, &tp.a, sizeof(tp.a), tp.block, tp.grid, tp.lds);
     key += graph_key(3, &vp.a, sizeof(vp.a), vp.block, vp.grid, vp.lds);

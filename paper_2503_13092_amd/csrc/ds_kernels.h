@@ -75,6 +75,15 @@ struct TrackArgs {
     int cmax;
     int *r_seed, *r_cand, *r_nhits, *r_h0, *r_h1, *r_h2, *r_h3;
     float *r_x, *r_y, *r_tx, *r_ty, *r_qop, *r_chi2, *r_score;
+    // fused vertexing (ds_process): kept tracks of an event go to LDS as they are written
+    int tcap;            // LDS capacity for kept tracks of one event
+    float score_max;
+    int vcap;
+    int *vcount, *vi, *vj;
+    float *vx, *vy, *vz, *vdoca;
+    int *voverflow, *vflags;
+    float *m_pipi, *m_ppi, *line0, *line1, *line2, *line3;
+    const float *WL;
     int nb;              // bins per layer
     float u0, inv_bw;    // bin = floor((u - u0) * inv_bw), clamped
 };
@@ -509,8 +518,8 @@ __device__ inline StoredTrack stored_track(const TrackArgs &a, const DevGeom &G,
 }
 
 // Write the selected candidate (LDS positions bp, -1 = none) as seed i's track.
-__device__ inline void write_track(const TrackArgs &a, const DevGeom &G, int i, const SeedConst &sc,
-                                   const float *hu_s, const uint16_t *hidx_s, const int bp[4], int c)
+__device__ inline StoredTrack write_track(const TrackArgs &a, const DevGeom &G, int i, const SeedConst &sc,
+                                          const float *hu_s, const uint16_t *hidx_s, const int bp[4], int c)
 {
     const int mask = (bp[0] >= 0 ? 1 : 0) | (bp[1] >= 0 ? 2 : 0) | (bp[2] >= 0 ? 4 : 0) | 8;
     const int n = __popc(mask);
@@ -533,6 +542,7 @@ __device__ inline void write_track(const TrackArgs &a, const DevGeom &G, int i, 
     a.nhits[i] = n;
     if (a.cand) a.cand[i] = c;
     if (a.fuse_mlp) a.score[i] = t.score;
+    return t;
 }
 
 // One row per (seed, candidate index) of the candidate-scoring mode.
@@ -635,7 +645,100 @@ __device__ inline bool stage_hits(const TrackArgs &a, int hb, const int hl[4], i
     return true;
 }
 
-template <int BLOCK, bool CANDS>
+__device__ inline void unrank_pair(int k, int n, int &pa, int &pb);
+__device__ inline bool pca64(const DevGeom &G, double x1, double y1, double tx1, double ty1, double g1, double x2,
+                             double y2, double tx2, double ty2, double g2, double &vx, double &vy, double &vz,
+                             double &doca, double &s_out, double &t_out);
+__device__ inline void vertex_extras(const DevGeom &G, const float *WLg, float4 A, float4 B, double g1, double g2,
+                                     float q1, float q2, double s, double t, float4 V, float out[6]);
+
+// Vertexing of one event by the whole workgroup, from the kept tracks in LDS
+// (slot order): pairs (a < b) in row-major chunks of BLOCK, float32
+// prescreen, float64 Newton PCA of the survivors, order-preserving output.
+template <int BLOCK>
+__device__ inline void vertex_event_block(const TrackArgs &a, const DevGeom &G, int e, int s0, int n,
+                                          const float4 *kst, const float *kq, const int *kslot, int *qk, int *qpass,
+                                          float4 *qres, float2 *qst, int *s_wsum)
+{
+    const int tid = threadIdx.x;
+    const bool curved = (G.fp != 0.0);
+    const bool extras = a.m_pipi != nullptr;
+    const int npairs = n * (n - 1) / 2;
+    int out_n = 0;
+    for (int chunk = 0; chunk < npairs; chunk += BLOCK) {
+        const int k = chunk + tid;
+        int pa = 0, pb = 0;
+        bool surv = false;
+        if (k < npairs) {
+            unrank_pair(k, n, pa, pb);
+            surv = ((kslot[pa] ^ kslot[pb]) & 1) != 0;
+            if (surv && !curved) {
+                const float4 A = kst[pa], B = kst[pb];
+                const float wx = A.x - B.x, wy = A.y - B.y;
+                const float nx = A.w - B.w, ny = B.z - A.z;
+                const float nz = fmaf(A.z, B.w, -(A.w * B.z));
+                const float wn = fmaf(wx, nx, wy * ny);
+                const float nn = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
+                surv = (nn < 1e-6f) || (wn * wn < G.prescreen_thr2 * nn);
+            }
+        }
+        int tot;
+        const int pos = block_exclusive_scan<BLOCK>(surv ? 1 : 0, s_wsum, &tot);
+        if (surv) qk[pos] = (pa << 16) | pb;
+        lds_barrier();
+        int pass = 0;
+        if (tid < tot) {
+            const int ia = qk[tid] >> 16, ib = qk[tid] & 0xffff;
+            const float4 A = kst[ia], B = kst[ib];
+            const double g1 = -G.fp * (G.gc0 + G.gc1 * ((double)kq[ia] * 1e-3));
+            const double g2 = -G.fp * (G.gc0 + G.gc1 * ((double)kq[ib] * 1e-3));
+            double vx, vy, vz, dd, ps, pt;
+            const bool good = pca64(G, A.x, A.y, A.z, A.w, g1, B.x, B.y, B.z, B.w, g2, vx, vy, vz, dd, ps, pt);
+            pass = (good && (dd < G.doca_max)) ? 1 : 0;
+            qres[tid] = make_float4((float)vx, (float)vy, (float)vz, (float)dd);
+            qst[tid] = make_float2((float)ps, (float)pt);
+        }
+        int tot2;
+        const int opos = block_exclusive_scan<BLOCK>(pass, s_wsum, &tot2);
+        if (pass) {
+            const int m = out_n + opos;
+            if (m < a.vcap) {
+                const size_t o = (size_t)e * (size_t)a.vcap + (size_t)m;
+                const int ia = qk[tid] >> 16, ib = qk[tid] & 0xffff;
+                a.vi[o] = kslot[ia] >> 1;
+                a.vj[o] = kslot[ib] >> 1;
+                const float4 R = qres[tid];
+                a.vx[o] = R.x;
+                a.vy[o] = R.y;
+                a.vz[o] = R.z;
+                a.vdoca[o] = R.w;
+                if (extras) {
+                    const float4 TA = kst[ia], TB = kst[ib];
+                    const double g1 = -G.fp * (G.gc0 + G.gc1 * ((double)kq[ia] * 1e-3));
+                    const double g2 = -G.fp * (G.gc0 + G.gc1 * ((double)kq[ib] * 1e-3));
+                    const float2 ST = qst[tid];
+                    float ex[6];
+                    vertex_extras(G, a.WL, TA, TB, g1, g2, a.sqop[s0 + (kslot[ia] >> 1)],
+                                  a.sqop[s0 + (kslot[ib] >> 1)], ST.x, ST.y, R, ex);
+                    a.m_pipi[o] = ex[0];
+                    a.m_ppi[o] = ex[1];
+                    a.line0[o] = ex[2];
+                    a.line1[o] = ex[3];
+                    a.line2[o] = ex[4];
+                    a.line3[o] = ex[5];
+                }
+            }
+        }
+        out_n += tot2;
+        lds_barrier();
+    }
+    if (tid == 0) {
+        a.vcount[e] = out_n < a.vcap ? out_n : a.vcap;
+        if (out_n > a.vcap) atomicAdd(a.voverflow, out_n - a.vcap);
+    }
+}
+
+template <int BLOCK, bool CANDS, bool VTX>
 __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -655,7 +758,16 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
     uint32_t *it_desc = reinterpret_cast<uint32_t *>(smem + off);
     off = (off + (size_t)a.icap * 4 + 15) & ~(size_t)15;
     unsigned long long *it_hits = reinterpret_cast<unsigned long long *>(smem + off);
-    __shared__ int s_ev, s_bad, s_nacc, s_nitems;
+    off += (size_t)a.icap * 8;
+    // fused vertexing: kept tracks of the event, and a pair queue aliasing the item buffers
+    float4 *kst = reinterpret_cast<float4 *>(smem + off);
+    float *kq = reinterpret_cast<float *>(smem + off + (size_t)a.tcap * 16);
+    int *kslot = reinterpret_cast<int *>(smem + off + (size_t)a.tcap * 20);
+    int *qk = reinterpret_cast<int *>(it_desc);
+    int *qpass = qk + BLOCK;
+    float4 *qres = reinterpret_cast<float4 *>(it_hits);
+    float2 *qst = reinterpret_cast<float2 *>(it_hits + 2 * BLOCK);
+    __shared__ int s_ev, s_bad, s_nacc, s_nitems, s_nkept;
     __shared__ int s_wsum[BLOCK / 64];
     const int tid = threadIdx.x;
     const int per_r3 = G.nw[0] * G.nw[1] * G.nw[2];
@@ -687,20 +799,24 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
         else if (nh > a.hcap || nh > a.max_hits || s1 - s0 > a.max_seeds) bad = F_CAPACITY;
         if (bad) {
             if (tid == 0) atomicOr(a.flags, bad);
+            if (VTX && tid == 0) a.vcount[e] = 0;
             if (seeds_ok)
                 for (int i = s0 + tid; i < s1; i += BLOCK) write_empty_track(a, i);
             lds_barrier();
             continue;
         }
         if (s1 == s0) {
+            if (VTX && tid == 0) a.vcount[e] = 0;
             lds_barrier();
             continue;
         }
+        if (VTX && tid == 0) s_nkept = 0;
         int hl[4];
 #pragma unroll
         for (int L = 0; L < 4; ++L) hl[L] = ho[L] - ho[0];
         if (!stage_hits<BLOCK>(a, ho[0], hl, nh, hu_s, hidx_s, E, &s_bad, s_wsum)) {
             if (tid == 0) atomicOr(a.flags, F_NONFINITE);
+            if (VTX && tid == 0) a.vcount[e] = 0;
             for (int i = s0 + tid; i < s1; i += BLOCK) write_empty_track(a, i);
             lds_barrier();
             continue;
@@ -777,6 +893,8 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
             }
             lds_barrier();
             // phase C: lane per seed, write the winner (and its ghost score)
+            bool kept = false;
+            StoredTrack t;
             if (!CANDS && tid < nacc) {
                 const unsigned long long key = s_key[tid];
                 if (key == ~0ull) {
@@ -790,12 +908,27 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
                         const int v = (int)((hp >> (16 * L)) & 0xffffull);
                         bp[L] = v == 0xffff ? -1 : v;
                     }
-                    write_track(a, G, i, s_c[tid], hu_s, hidx_s, bp, c);
+                    t = write_track(a, G, i, s_c[tid], hu_s, hidx_s, bp, c);
+                    kept = VTX && t.score < a.score_max;
                 }
+            }
+            if (VTX) {
+                // kept tracks appended in slot order
+                int ktot;
+                const int kpos = block_exclusive_scan<BLOCK>(kept ? 1 : 0, s_wsum, &ktot);
+                if (kept) {
+                    const int k = s_nkept + kpos;
+                    kst[k] = make_float4(t.x, t.y, t.tx, t.ty);
+                    kq[k] = t.qop;
+                    kslot[k] = ((i - s0) << 1) | (a.sqop[i] > 0.0f ? 1 : 0);
+                }
+                lds_barrier();
+                if (tid == 0) s_nkept += ktot;
             }
             lds_barrier();
             sc0 += nacc;
         }
+        if (VTX) vertex_event_block<BLOCK>(a, G, e, s0, s_nkept, kst, kq, kslot, qk, qpass, qres, qst, s_wsum);
     }
     if (a.ev_single < 0 && tid == 0) {
         __threadfence();
