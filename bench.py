@@ -12,7 +12,6 @@ the dominant kernel (tracking) from its HIP-event-timed average duration; and
 the FP64 CPU oracle timed on the host's cores.
 """
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -34,10 +33,8 @@ WORKLOADS = {
 
 
 def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for p in ("paper_2503_13092_amd/csrc/ds_kernels.h", "paper_2503_13092_amd/csrc/ds_api.hip"):
-        h.update(open(os.path.join(ROOT, p), "rb").read())
-    return h.hexdigest()[:16]
+    from paper_2503_13092_amd.build_lib import kernel_source_hash as h
+    return h()
 
 
 def track_bytes_per_event(batch) -> float:

@@ -30,6 +30,17 @@ def build(verbose: bool = False, extra=()) -> str:
     return LIB
 
 
+def kernel_source_hash() -> str:
+    """Short hash of the kernel sources; ties a stored profile to the code it
+    was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for p in (os.path.join(HERE, "csrc", "ds_kernels.h"), os.path.join(HERE, "csrc", "ds_api.hip")):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def is_stale() -> bool:
     if not os.path.exists(LIB):
         return True

@@ -365,8 +365,8 @@ __device__ inline bool seed_frame(const DevGeom &G, float fsx, float fsy, float 
 // Every valid candidate through one UTbX hit (rank r3, LDS position p3), in
 // candidate-index order: refined windows in UTaX, UTaU, UTbV, the <= 4 option
 // tuples, their fits.  visit(n, c, alpha, beta, chi2, bp) is called for each.
-template <typename Visit>
-__device__ inline void item_candidates(const DevGeom &G, const TrackArgs &a, const float *hu_s,
+template <int N0, int N1, int N2, typename Visit>
+__device__ inline void item_candidates_n(const DevGeom &G, const TrackArgs &a, const float *hu_s,
                                        const uint16_t *hidx_s, const int *E, const SeedConst &sc, int r3, int p3,
                                        Visit &&visit)
 {
@@ -395,12 +395,15 @@ __device__ inline void item_candidates(const DevGeom &G, const TrackArgs &a, con
             const float u = hu_s[p];
             const double d = fabs((double)u - m[L]);
             if (!(d <= W2)) continue;
+            const int NL = L == 0 ? N0 : (L == 1 ? N1 : N2);
             if (before(hu_s, hidx_s, d, u, p, d0[L], p0k[L])) {
-                d1[L] = d0[L];
-                p1k[L] = p0k[L];
+                if (NL > 1) {
+                    d1[L] = d0[L];
+                    p1k[L] = p0k[L];
+                }
                 d0[L] = d;
                 p0k[L] = p;
-            } else if (before(hu_s, hidx_s, d, u, p, d1[L], p1k[L])) {
+            } else if (NL > 1 && before(hu_s, hidx_s, d, u, p, d1[L], p1k[L])) {
                 d1[L] = d;
                 p1k[L] = p;
             }
@@ -417,15 +420,15 @@ __device__ inline void item_candidates(const DevGeom &G, const TrackArgs &a, con
     double rho[4];
     rho[3] = rho3;
 #pragma unroll
-    for (int i0 = 0; i0 < MAX_CLOSEST; ++i0) {
+    for (int i0 = 0; i0 < N0; ++i0) {
         if (i0 >= (nA[0] > 0 ? nA[0] : 1)) continue;
         const int p0 = A[0][i0];
 #pragma unroll
-        for (int i1 = 0; i1 < MAX_CLOSEST; ++i1) {
+        for (int i1 = 0; i1 < N1; ++i1) {
             if (i1 >= (nA[1] > 0 ? nA[1] : 1)) continue;
             const int p1 = A[1][i1];
 #pragma unroll
-            for (int i2 = 0; i2 < MAX_CLOSEST; ++i2) {
+            for (int i2 = 0; i2 < N2; ++i2) {
                 if (i2 >= (nA[2] > 0 ? nA[2] : 1)) continue;
                 const int p2 = A[2][i2];
                 const int mask = 8 | (p0 >= 0 ? 1 : 0) | (p1 >= 0 ? 2 : 0) | (p2 >= 0 ? 4 : 0);
@@ -441,6 +444,19 @@ __device__ inline void item_candidates(const DevGeom &G, const TrackArgs &a, con
             }
         }
     }
+}
+
+// The paper's (1, 2, 2) closest hits are compiled on their own; other settings
+// take the generic (<= 2, <= 2, <= 2) enumeration.  Same visiting order.
+template <typename Visit>
+__device__ inline void item_candidates(const DevGeom &G, const TrackArgs &a, const float *hu_s,
+                                       const uint16_t *hidx_s, const int *E, const SeedConst &sc, int r3, int p3,
+                                       Visit &&visit)
+{
+    if (G.ncl[0] == 1 && G.ncl[1] == 2 && G.ncl[2] == 2)
+        item_candidates_n<1, 2, 2>(G, a, hu_s, hidx_s, E, sc, r3, p3, visit);
+    else
+        item_candidates_n<MAX_CLOSEST, MAX_CLOSEST, MAX_CLOSEST>(G, a, hu_s, hidx_s, E, sc, r3, p3, visit);
 }
 
 // Rank of the UTbX hit at p3 among the seed's first-window hits (by the
