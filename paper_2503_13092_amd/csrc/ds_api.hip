@@ -20,7 +20,7 @@ namespace {
 constexpr int MAX_STREAM_SLOTS = 64;
 constexpr int MAX_GRAPHS = 64;
 constexpr int VTX_PPT = 4;
-constexpr int ITEMS_PER_SEED = 4;
+constexpr int ITEMS_PER_SEED = 3;
 constexpr int CLONE_BLOCK = 256;
 constexpr size_t LDS_LIMIT = 160 * 1024 - 256;   // gfx950: 160 KiB per workgroup, minus static use
 constexpr float PRESCREEN_MARGIN = 0.1f;         // mm, see the float32 error bound of the pair prescreen
@@ -138,11 +138,11 @@ template <int B>
 hipError_t launch_track_b(const ds::TrackArgs &a, const ds::DevGeom &G, int grid, size_t lds, hipStream_t s)
 {
     if (a.cmax > 0)
-        hipLaunchKernelGGL((ds::k_track<B, true, false>), dim3(grid), dim3(B), lds, s, a, G);
+        hipLaunchKernelGGL((ds::k_track<B, true, false>), dim3(grid), dim3(B), lds, s, ds::TrackKernArgs{a, G});
     else if (a.vcount)
-        hipLaunchKernelGGL((ds::k_track<B, false, true>), dim3(grid), dim3(B), lds, s, a, G);
+        hipLaunchKernelGGL((ds::k_track<B, false, true>), dim3(grid), dim3(B), lds, s, ds::TrackKernArgs{a, G});
     else
-        hipLaunchKernelGGL((ds::k_track<B, false, false>), dim3(grid), dim3(B), lds, s, a, G);
+        hipLaunchKernelGGL((ds::k_track<B, false, false>), dim3(grid), dim3(B), lds, s, ds::TrackKernArgs{a, G});
     return hipGetLastError();
 }
 

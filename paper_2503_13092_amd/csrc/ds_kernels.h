@@ -128,7 +128,27 @@ struct VertexArgs {
     const float *WL;     // trigger-line networks, 4 x (W1[32][12], b1[32], W2[32], b2)
 };
 
+// The tracking kernel's arguments as one block.
+struct TrackKernArgs {
+    TrackArgs a;
+    DevGeom G;
+};
+
 // ----------------------------------------------------------------- helpers
+
+// The launch's argument block, reached through an opaque copy of its address.
+// Loads through the returned reference cannot move above the call, so a
+// persistent kernel re-reads uniform arguments (scalar loads) in the phase that
+// uses them instead of keeping all of them live, and spilled to vector lanes,
+// across its whole loop.
+template <typename T>
+__device__ inline const T &kernel_args()
+{
+    typedef const __attribute__((address_space(4))) T *cptr;
+    cptr p = (cptr)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(p));
+    return *(const T *)p;
+}
 
 // Workgroup barrier ordering LDS traffic only: unlike __syncthreads it does not
 // wait for the wave's outstanding global stores.
@@ -217,39 +237,51 @@ struct SeedConst {
     uint16_t lo, hi; // LDS range of the UTbX buckets covering the first window
 };
 
-// Least squares of residuals rho_L over a valid layer set (mask 11, 13, 14 or 15).
-__device__ inline void fit_residuals(const DevGeom &G, int mask, const double rho[4], double &alpha, double &beta,
-                                     double &chi2)
+// Least-squares constants of one valid layer set (mask 11, 13, 14 or 15):
+// sum of dz, 1/det of the normal equations, 1/n, and the 0/1 layer weights.
+struct FitConst {
+    double sz, idet, in, n;
+    double w[4];
+};
+
+__device__ inline FitConst fit_const(const DevGeom &G, int mask)
 {
-    int k = (mask == 15) ? 3 : (mask == 14) ? 2 : (mask == 13) ? 1 : 0;
-    double sz = G.fit_sz[0], idet = G.fit_inv_det[0], in = G.fit_inv_n[0];
-    sz = (k == 1) ? G.fit_sz[1] : sz;
-    idet = (k == 1) ? G.fit_inv_det[1] : idet;
-    in = (k == 1) ? G.fit_inv_n[1] : in;
-    sz = (k == 2) ? G.fit_sz[2] : sz;
-    idet = (k == 2) ? G.fit_inv_det[2] : idet;
-    in = (k == 2) ? G.fit_inv_n[2] : in;
-    sz = (k == 3) ? G.fit_sz[3] : sz;
-    idet = (k == 3) ? G.fit_inv_det[3] : idet;
-    in = (k == 3) ? G.fit_inv_n[3] : in;
-    double sr = 0.0, szr = 0.0, n = 0.0;
+    const int k = (mask == 15) ? 3 : (mask == 14) ? 2 : (mask == 13) ? 1 : 0;
+    FitConst f;
+    f.sz = G.fit_sz[0];
+    f.idet = G.fit_inv_det[0];
+    f.in = G.fit_inv_n[0];
+#pragma unroll
+    for (int j = 1; j < 4; ++j) {
+        f.sz = (k == j) ? G.fit_sz[j] : f.sz;
+        f.idet = (k == j) ? G.fit_inv_det[j] : f.idet;
+        f.in = (k == j) ? G.fit_inv_n[j] : f.in;
+    }
+    f.n = (mask == 15) ? 4.0 : 3.0;
+#pragma unroll
+    for (int L = 0; L < 4; ++L) f.w[L] = ((mask >> L) & 1) ? 1.0 : 0.0;
+    return f;
+}
+
+// Straight-line least squares rho_L ~ alpha + beta dz_L over the layer set of
+// f; rho_L must be 0 for a layer outside the set (it then adds nothing to the
+// sums, and its weight 0 keeps it out of chi2).
+__device__ inline void fit_set(const DevGeom &G, const FitConst &f, const double rho[4], double &alpha,
+                               double &beta, double &chi2)
+{
+    double sr = 0.0, szr = 0.0;
 #pragma unroll
     for (int L = 0; L < 4; ++L) {
-        if ((mask >> L) & 1) {
-            sr += rho[L];
-            szr = fma(G.dz[L], rho[L], szr);
-            n += 1.0;
-        }
+        sr += rho[L];
+        szr = fma(G.dz[L], rho[L], szr);
     }
-    beta = (n * szr - sz * sr) * idet;
-    alpha = (sr - beta * sz) * in;
+    beta = (f.n * szr - f.sz * sr) * f.idet;
+    alpha = (sr - beta * f.sz) * f.in;
     double c2 = 0.0;
 #pragma unroll
     for (int L = 0; L < 4; ++L) {
-        if ((mask >> L) & 1) {
-            double r = rho[L] - alpha - beta * G.dz[L];
-            c2 = fma(r, r, c2);
-        }
+        const double r = rho[L] - alpha - beta * G.dz[L];
+        c2 = fma(r, r * f.w[L], c2);
     }
     chi2 = c2 * G.inv_sigma2;
 }
@@ -343,6 +375,13 @@ __device__ inline void write_empty_track(const TrackArgs &a, int i)
     if (a.cand) a.cand[i] = -1;
 }
 
+// First-window centre in UTbX: the kinked prediction of the seed.  One
+// expression for every use, so that membership tests agree bit for bit.
+__device__ inline double window1_centre(const DevGeom &G, double c3, double q)
+{
+    return fma(G.mk * q, G.zm - G.zl[3], c3);
+}
+
 // Seed constants of the residual frame and the first-window centre / width.
 __device__ inline bool seed_frame(const DevGeom &G, float fsx, float fsy, float fstx, float fsty, float fsq,
                                   SeedConst &sc, double &m3, double &W1)
@@ -358,7 +397,7 @@ __device__ inline bool seed_frame(const DevGeom &G, float fsx, float fsy, float 
     }
     sc.q = fsq;
     W1 = fma(G.w1c1, fabs(sq), G.w1c0);
-    m3 = sc.c[3] + G.mk * sq * (G.zm - G.zl[3]);
+    m3 = window1_centre(G, sc.c[3], sq);
     return true;
 }
 
@@ -417,29 +456,33 @@ __device__ inline void item_candidates_n(const DevGeom &G, const TrackArgs &a, c
         A[L][1] = G.ncl[L] >= 2 ? p1k[L] : -1;
         nA[L] = (A[L][0] >= 0 ? 1 : 0) + (A[L][1] >= 0 ? 1 : 0);
     }
-    double rho[4];
-    rho[3] = rho3;
+    // every option tuple of the item has the same layer set: a layer either
+    // has hits (all its options are hits) or has the single option "no hit"
+    const int mask = 8 | (nA[0] > 0 ? 1 : 0) | (nA[1] > 0 ? 2 : 0) | (nA[2] > 0 ? 4 : 0);
+    const int n = __popc(mask);
+    if (n < 3 || (mask & 3) == 0) return;
+    const FitConst fc = fit_const(G, mask);
+    double r0[N0], r1[N1], r2[N2];
+#pragma unroll
+    for (int i = 0; i < N0; ++i) r0[i] = A[0][i] >= 0 ? (double)hu_s[A[0][i]] - sc.c[0] : 0.0;
+#pragma unroll
+    for (int i = 0; i < N1; ++i) r1[i] = A[1][i] >= 0 ? (double)hu_s[A[1][i]] - sc.c[1] : 0.0;
+#pragma unroll
+    for (int i = 0; i < N2; ++i) r2[i] = A[2][i] >= 0 ? (double)hu_s[A[2][i]] - sc.c[2] : 0.0;
+    const int o0 = nA[0] > 0 ? nA[0] : 1, o1 = nA[1] > 0 ? nA[1] : 1, o2 = nA[2] > 0 ? nA[2] : 1;
 #pragma unroll
     for (int i0 = 0; i0 < N0; ++i0) {
-        if (i0 >= (nA[0] > 0 ? nA[0] : 1)) continue;
-        const int p0 = A[0][i0];
+        if (i0 >= o0) continue;
 #pragma unroll
         for (int i1 = 0; i1 < N1; ++i1) {
-            if (i1 >= (nA[1] > 0 ? nA[1] : 1)) continue;
-            const int p1 = A[1][i1];
+            if (i1 >= o1) continue;
 #pragma unroll
             for (int i2 = 0; i2 < N2; ++i2) {
-                if (i2 >= (nA[2] > 0 ? nA[2] : 1)) continue;
-                const int p2 = A[2][i2];
-                const int mask = 8 | (p0 >= 0 ? 1 : 0) | (p1 >= 0 ? 2 : 0) | (p2 >= 0 ? 4 : 0);
-                const int n = __popc(mask);
-                if (n < 3 || (p0 < 0 && p1 < 0)) continue;
-                rho[0] = p0 >= 0 ? (double)hu_s[p0] - sc.c[0] : 0.0;
-                rho[1] = p1 >= 0 ? (double)hu_s[p1] - sc.c[1] : 0.0;
-                rho[2] = p2 >= 0 ? (double)hu_s[p2] - sc.c[2] : 0.0;
+                if (i2 >= o2) continue;
+                const double rho[4] = {r0[i0], r1[i1], r2[i2], rho3};
                 double al, be, c2;
-                fit_residuals(G, mask, rho, al, be, c2);
-                const int bp[4] = {p0, p1, p2, p3};
+                fit_set(G, fc, rho, al, be, c2);
+                const int bp[4] = {A[0][i0], A[1][i1], A[2][i2], p3};
                 visit(n, ((r3 * G.nw[0] + i0) * G.nw[1] + i1) * G.nw[2] + i2, al, be, c2, bp);
             }
         }
@@ -464,9 +507,8 @@ __device__ inline void item_candidates(const DevGeom &G, const TrackArgs &a, con
 __device__ inline int first_window_rank(const DevGeom &G, const float *hu_s, const uint16_t *hidx_s,
                                         const SeedConst &sc, int p3)
 {
-    const double q = sc.q;
-    const double W1 = fma(G.w1c1, fabs(q), G.w1c0);
-    const double m3 = sc.c[3] + G.mk * q * (G.zm - G.zl[3]);
+    const double W1 = fma(G.w1c1, fabs((double)sc.q), G.w1c0);
+    const double m3 = window1_centre(G, sc.c[3], (double)sc.q);
     const float u3 = hu_s[p3];
     const double d3 = fabs((double)u3 - m3);
     if (!(d3 <= W1)) return -1;
@@ -543,7 +585,7 @@ __device__ inline StoredTrack write_track(const TrackArgs &a, const DevGeom &G, 
 #pragma unroll
     for (int L = 0; L < 4; ++L) rho[L] = bp[L] >= 0 ? (double)hu_s[bp[L]] - sc.c[L] : 0.0;
     double al, be, c2;
-    fit_residuals(G, mask, rho, al, be, c2);
+    fit_set(G, fit_const(G, mask), rho, al, be, c2);
     const StoredTrack t = stored_track(a, G, i, n, al, be, c2, hu_s, bp, a.fuse_mlp != 0);
     a.x[i] = t.x;
     a.y[i] = t.y;
@@ -755,16 +797,17 @@ __device__ inline void vertex_event_block(const TrackArgs &a, const DevGeom &G, 
 }
 
 template <int BLOCK, bool CANDS, bool VTX>
-__global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
+__global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
 {
+    const TrackArgs &a0 = kernel_args<TrackKernArgs>().a;
     extern __shared__ __align__(16) unsigned char smem[];
     size_t off = 0;
     float *hu_s = reinterpret_cast<float *>(smem + off);
-    off += (size_t)a.hcap * 4;
+    off += (size_t)a0.hcap * 4;
     uint16_t *hidx_s = reinterpret_cast<uint16_t *>(smem + off);
-    off = (off + (size_t)a.hcap * 2 + 15) & ~(size_t)15;
+    off = (off + (size_t)a0.hcap * 2 + 15) & ~(size_t)15;
     int *E = reinterpret_cast<int *>(smem + off);
-    off = (off + (size_t)(4 * a.nb + 1) * 4 + 15) & ~(size_t)15;
+    off = (off + (size_t)(4 * a0.nb + 1) * 4 + 15) & ~(size_t)15;
     SeedConst *s_c = reinterpret_cast<SeedConst *>(smem + off);
     off += (size_t)BLOCK * sizeof(SeedConst);
     unsigned long long *s_key = reinterpret_cast<unsigned long long *>(smem + off);
@@ -772,13 +815,13 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
     int *s_base = reinterpret_cast<int *>(smem + off);
     off = (off + (size_t)BLOCK * 4 + 15) & ~(size_t)15;
     uint32_t *it_desc = reinterpret_cast<uint32_t *>(smem + off);
-    off = (off + (size_t)a.icap * 4 + 15) & ~(size_t)15;
+    off = (off + (size_t)a0.icap * 4 + 15) & ~(size_t)15;
     unsigned long long *it_hits = reinterpret_cast<unsigned long long *>(smem + off);
-    off += (size_t)a.icap * 8;
+    off += (size_t)a0.icap * 8;
     // fused vertexing: kept tracks of the event, and a pair queue aliasing the item buffers
     float4 *kst = reinterpret_cast<float4 *>(smem + off);
-    float *kq = reinterpret_cast<float *>(smem + off + (size_t)a.tcap * 16);
-    int *kslot = reinterpret_cast<int *>(smem + off + (size_t)a.tcap * 20);
+    float *kq = reinterpret_cast<float *>(smem + off + (size_t)a0.tcap * 16);
+    int *kslot = reinterpret_cast<int *>(smem + off + (size_t)a0.tcap * 20);
     int *qk = reinterpret_cast<int *>(it_desc);
     int *qpass = qk + BLOCK;
     float4 *qres = reinterpret_cast<float4 *>(it_hits);
@@ -786,9 +829,11 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
     __shared__ int s_ev, s_bad, s_nacc, s_nitems, s_nkept;
     __shared__ int s_wsum[BLOCK / 64];
     const int tid = threadIdx.x;
-    const int per_r3 = G.nw[0] * G.nw[1] * G.nw[2];
 
     for (int iter = 0;; ++iter) {
+        const TrackKernArgs &Ke = kernel_args<TrackKernArgs>();
+        const TrackArgs &a = Ke.a;
+        const DevGeom &G = Ke.G;
         if (tid == 0) {
             int e;
             if (a.ev_single >= 0)
@@ -840,12 +885,15 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
 
         // seeds in chunks of at most BLOCK, shortened so that their items fit
         for (int sc0 = s0; sc0 < s1;) {
+            const TrackKernArgs &Kc = kernel_args<TrackKernArgs>();
+            const TrackArgs &a = Kc.a;
+            const DevGeom &G = Kc.G;
             if (tid == 0) {
                 s_nacc = min(BLOCK, s1 - sc0);
                 s_nitems = 0;
             }
             // phase A: lane per seed, the UTbX bucket range of its first window;
-            // every hit of the range becomes an item (seed, hit)
+            // every hit of the range inside the window becomes an item (seed, hit)
             const int i = sc0 + tid;
             const bool have = i < s1;
             SeedConst sc;
@@ -861,14 +909,15 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
             }
             sc.lo = (uint16_t)p_lo;
             sc.hi = (uint16_t)p_hi;
+            int n_win = 0;
+            for (int k = 0; k < n_rng; ++k) n_win += fabs((double)hu_s[p_lo + k] - m3) <= W1 ? 1 : 0;
             int tot;
-            const int excl = block_exclusive_scan<BLOCK>(n_rng, s_wsum, &tot);
-            bool acc = have && (excl + n_rng <= a.icap);
+            const int excl = block_exclusive_scan<BLOCK>(n_win, s_wsum, &tot);
+            bool acc = have && (excl + n_win <= a.icap);
             if (tid == 0 && have && !acc) {
-                // one seed alone overflows the item buffer: truncate its range (flagged)
+                // one seed alone overflows the item buffer: keep its first items (flagged)
                 atomicOr(a.flags, F_CAPACITY);
-                n_rng = a.icap;
-                sc.hi = (uint16_t)(p_lo + n_rng);
+                n_win = a.icap;
                 acc = true;
             }
             if (have && !acc) atomicMin(&s_nacc, tid);
@@ -876,13 +925,19 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
                 s_c[tid] = sc;
                 s_key[tid] = ~0ull;
                 s_base[tid] = excl;
-                atomicMax(&s_nitems, excl + n_rng);
-                for (int k = 0; k < n_rng; ++k) it_desc[excl + k] = ((uint32_t)tid << 16) | (uint32_t)(p_lo + k);
+                atomicMax(&s_nitems, excl + n_win);
+                for (int k = 0, w = 0; k < n_rng && w < n_win; ++k) {
+                    if (fabs((double)hu_s[p_lo + k] - m3) <= W1)
+                        it_desc[excl + w++] = ((uint32_t)tid << 16) | (uint32_t)(p_lo + k);
+                }
             }
             lds_barrier();
             const int nacc = s_nacc, n_items = s_nitems;
             // phase B: lane per (seed, UTbX hit) item
             for (int it = tid; it < n_items; it += BLOCK) {
+                const TrackKernArgs &Ki = kernel_args<TrackKernArgs>();
+                const TrackArgs &a = Ki.a;
+                const DevGeom &G = Ki.G;
                 const uint32_t d = it_desc[it];
                 const int sl = (int)(d >> 16), p3 = (int)(d & 0xffffu);
                 const SeedConst scs = s_c[sl];
@@ -912,6 +967,7 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
             bool kept = false;
             StoredTrack t;
             if (!CANDS && tid < nacc) {
+                const int per_r3 = G.nw[0] * G.nw[1] * G.nw[2];
                 const unsigned long long key = s_key[tid];
                 if (key == ~0ull) {
                     write_empty_track(a, i);
@@ -944,8 +1000,12 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackArgs a, DevGeom G)
             lds_barrier();
             sc0 += nacc;
         }
-        if (VTX) vertex_event_block<BLOCK>(a, G, e, s0, s_nkept, kst, kq, kslot, qk, qpass, qres, qst, s_wsum);
+        if (VTX) {
+            const TrackKernArgs &Kv = kernel_args<TrackKernArgs>();
+            vertex_event_block<BLOCK>(Kv.a, Kv.G, e, s0, s_nkept, kst, kq, kslot, qk, qpass, qres, qst, s_wsum);
+        }
     }
+    const TrackArgs &a = kernel_args<TrackKernArgs>().a;
     if (a.ev_single < 0 && tid == 0) {
         __threadfence();
         const int done = atomicAdd(&a.counter[1], 1);
