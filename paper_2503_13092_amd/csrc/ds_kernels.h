@@ -630,24 +630,34 @@ __device__ inline void write_candidate_row(const TrackArgs &a, const DevGeom &G,
 // start of bucket b and E[4*nb] = count.  Hits are read HPT per lane per round
 // with all loads in flight; events of one round keep them in registers
 // between the counting and the placing pass.
-template <int BLOCK>
+template <int BLOCK, typename Between>
 __device__ inline bool stage_hits(const TrackArgs &a, int hb, const int hl[4], int nh, float *hu_s,
-                                  uint16_t *hidx_s, int *E, int *s_bad, int *s_wsum)
+                                  uint16_t *hidx_s, int *E, int *s_bad, int *s_wsum, Between &&between)
 {
     constexpr int HPT = 16;
     const int tid = threadIdx.x;
     const int NBT = 4 * a.nb;
-    for (int k = tid; k <= NBT; k += BLOCK) E[k] = 0;
-    if (tid == 0) *s_bad = 0;
-    lds_barrier();
     const int rounds = (nh + HPT * BLOCK - 1) / (HPT * BLOCK);
     float u[HPT];
+    // the first round's loads are in flight while the buckets are cleared and
+    // `between` runs (work of the event that needs no hits)
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) {
+        const int k = tid + j * BLOCK;
+        u[j] = (k < nh) ? a.hu[hb + k] : 0.0f;
+    }
+    for (int k = tid; k <= NBT; k += BLOCK) E[k] = 0;
+    if (tid == 0) *s_bad = 0;
+    between();
+    lds_barrier();
     for (int r = 0; r < rounds; ++r) {
         const int k0 = r * HPT * BLOCK + tid;
+        if (r > 0) {
 #pragma unroll
-        for (int j = 0; j < HPT; ++j) {
-            const int k = k0 + j * BLOCK;
-            u[j] = (k < nh) ? a.hu[hb + k] : 0.0f;
+            for (int j = 0; j < HPT; ++j) {
+                const int k = k0 + j * BLOCK;
+                u[j] = (k < nh) ? a.hu[hb + k] : 0.0f;
+            }
         }
         bool bad = false;
 #pragma unroll
@@ -796,6 +806,25 @@ __device__ inline void vertex_event_block(const TrackArgs &a, const DevGeom &G, 
     }
 }
 
+// Event of launch iteration `iter`: the work counter of a persistent launch,
+// or the one event of a per-event launch.
+__device__ inline int grab_event(const TrackArgs &a, int iter)
+{
+    if (a.ev_single >= 0) return iter == 0 ? a.ev_single : a.n_events;
+    return atomicAdd(&a.counter[0], 1);
+}
+
+// One whole wave: the event of iteration `iter` and its offsets into LDS,
+// s_nx = {event, seed_off[e], seed_off[e + 1], hit_off[4e .. 4e + 4]}.
+__device__ inline void fetch_event(const TrackArgs &a, int iter, int lane, int *s_nx)
+{
+    int en = 0;
+    if (lane == 0) en = grab_event(a, iter);
+    en = __builtin_amdgcn_readfirstlane(en);
+    if (lane == 0) s_nx[0] = en;
+    if (lane < 7 && en < a.n_events) s_nx[1 + lane] = lane < 2 ? a.seed_off[en + lane] : a.hit_off[4 * en + lane - 2];
+}
+
 template <int BLOCK, bool CANDS, bool VTX>
 __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
 {
@@ -826,30 +855,27 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
     int *qpass = qk + BLOCK;
     float4 *qres = reinterpret_cast<float4 *>(it_hits);
     float2 *qst = reinterpret_cast<float2 *>(it_hits + 2 * BLOCK);
-    __shared__ int s_ev, s_bad, s_nacc, s_nitems, s_nkept;
+    __shared__ int s_nx[8];   // next event and its offsets (fetch_event)
+    __shared__ int s_bad, s_nacc, s_nitems, s_nkept;
     __shared__ int s_wsum[BLOCK / 64];
     const int tid = threadIdx.x;
 
+    // The next event is fetched while this one is processed: its index (the
+    // work counter's atomic) and offsets arrive during phase B, where the
+    // last wave, the one with the fewest items, waits for them.
+    if (tid < 64) fetch_event(a0, 0, tid, s_nx);
+    lds_barrier();
     for (int iter = 0;; ++iter) {
         const TrackKernArgs &Ke = kernel_args<TrackKernArgs>();
         const TrackArgs &a = Ke.a;
         const DevGeom &G = Ke.G;
-        if (tid == 0) {
-            int e;
-            if (a.ev_single >= 0)
-                e = (iter == 0) ? a.ev_single : a.n_events;
-            else
-                e = atomicAdd(&a.counter[0], 1);
-            s_ev = e;
-        }
-        lds_barrier();
-        const int e = s_ev;
+        const int e = s_nx[0];
         if (e >= a.n_events) break;
-
-        const int s0 = a.seed_off[e], s1 = a.seed_off[e + 1];
+        const int s0 = s_nx[1], s1 = s_nx[2];
         int ho[5];
 #pragma unroll
-        for (int L = 0; L < 5; ++L) ho[L] = a.hit_off[4 * e + L];
+        for (int L = 0; L < 5; ++L) ho[L] = s_nx[3 + L];
+        lds_barrier();   // s_nx read by every wave before it is refilled
         const bool seeds_ok = (0 <= s0) && (s0 <= s1) && (s1 <= a.n_seeds);
         bool hits_ok = (0 <= ho[0]) && (ho[4] <= a.n_hits);
 #pragma unroll
@@ -863,11 +889,13 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
             if (VTX && tid == 0) a.vcount[e] = 0;
             if (seeds_ok)
                 for (int i = s0 + tid; i < s1; i += BLOCK) write_empty_track(a, i);
+            if (tid < 64) fetch_event(a, iter + 1, tid, s_nx);
             lds_barrier();
             continue;
         }
         if (s1 == s0) {
             if (VTX && tid == 0) a.vcount[e] = 0;
+            if (tid < 64) fetch_event(a, iter + 1, tid, s_nx);
             lds_barrier();
             continue;
         }
@@ -875,10 +903,24 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
         int hl[4];
 #pragma unroll
         for (int L = 0; L < 4; ++L) hl[L] = ho[L] - ho[0];
-        if (!stage_hits<BLOCK>(a, ho[0], hl, nh, hu_s, hidx_s, E, &s_bad, s_wsum)) {
+        // seed frames of the first chunk, computed while the hits are loading
+        auto first_frames = [&]() {
+            if (tid < s1 - s0) {
+                const int i = s0 + tid;
+                SeedConst sc;
+                double m3, W1;
+                if (!seed_frame(G, a.sx[i], a.sy[i], a.stx[i], a.sty[i], a.sqop[i], sc, m3, W1)) {
+                    atomicOr(a.flags, F_NONFINITE);
+                    sc.q = __int_as_float(0x7fc00000);   // NaN: no frame
+                }
+                s_c[tid] = sc;
+            }
+        };
+        if (!stage_hits<BLOCK>(a, ho[0], hl, nh, hu_s, hidx_s, E, &s_bad, s_wsum, first_frames)) {
             if (tid == 0) atomicOr(a.flags, F_NONFINITE);
             if (VTX && tid == 0) a.vcount[e] = 0;
             for (int i = s0 + tid; i < s1; i += BLOCK) write_empty_track(a, i);
+            if (tid < 64) fetch_event(a, iter + 1, tid, s_nx);
             lds_barrier();
             continue;
         }
@@ -900,11 +942,19 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
             double m3 = 0.0, W1 = 0.0;
             int n_rng = 0, p_lo = 0, p_hi = 0;
             if (have) {
-                if (seed_frame(G, a.sx[i], a.sy[i], a.stx[i], a.sty[i], a.sqop[i], sc, m3, W1)) {
+                bool ok;
+                if (sc0 == s0) {
+                    sc = s_c[tid];
+                    ok = sc.q == sc.q;
+                    m3 = window1_centre(G, sc.c[3], (double)sc.q);
+                    W1 = fma(G.w1c1, fabs((double)sc.q), G.w1c0);
+                } else {
+                    ok = seed_frame(G, a.sx[i], a.sy[i], a.stx[i], a.sty[i], a.sqop[i], sc, m3, W1);
+                    if (!ok) atomicOr(a.flags, F_NONFINITE);
+                }
+                if (ok) {
                     if (G.max_l3 > 0) bin_range(E, 3, a.nb, a.u0, a.inv_bw, m3, W1, p_lo, p_hi);
                     n_rng = p_hi - p_lo;
-                } else {
-                    atomicOr(a.flags, F_NONFINITE);
                 }
             }
             sc.lo = (uint16_t)p_lo;
@@ -933,6 +983,7 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
             }
             lds_barrier();
             const int nacc = s_nacc, n_items = s_nitems;
+            if (sc0 == s0 && tid >= BLOCK - 64) fetch_event(a, iter + 1, tid - (BLOCK - 64), s_nx);
             // phase B: lane per (seed, UTbX hit) item
             for (int it = tid; it < n_items; it += BLOCK) {
                 const TrackKernArgs &Ki = kernel_args<TrackKernArgs>();
