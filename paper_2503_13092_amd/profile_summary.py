@@ -21,6 +21,22 @@ COPY_KERNEL = "__amd_rocclr_copyBuffer"
 BENCH = "python $REPO/bench.py --steps {steps} --warmup 2 --no-plain --no-cpu-baseline --no-serve"
 
 
+SQ_SETS = (
+    "SQ_WAVE_CYCLES SQ_WAIT_ANY SQ_WAIT_INST_ANY SQ_WAIT_INST_LDS SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS "
+    "SQ_ACTIVE_INST_SCA SQ_ACTIVE_INST_ANY",
+    "SQ_INSTS_VALU SQ_THREAD_CYCLES_VALU SQ_LDS_BANK_CONFLICT SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_ADD_F64 "
+    "SQ_INSTS_VALU_MUL_F64 SQ_BUSY_CYCLES SQ_INSTS_LDS",
+    "SQ_WAVES SQ_INSTS_SALU SQ_INSTS_SMEM SQ_INST_CYCLES_SMEM SQ_INSTS_BRANCH SQ_LEVEL_WAVES SQ_CYCLES "
+    "SQ_INSTS_VALU_CVT",
+)
+SQ_BENCH = "python $REPO/bench.py --steps 3 --warmup 1 --no-plain --no-cpu-baseline --no-serve --no-copy-ceiling"
+
+
+def sq_commands(out_dir: str = "gpurun_out"):
+    return [f"rocprofv3 --pmc {c} --output-format csv -d $REPO/{out_dir}/pmc_sq{k} -o sq -- {SQ_BENCH}"
+            for k, c in enumerate(SQ_SETS)]
+
+
 def commands(out_dir: str = "gpurun_out", steps: int = 10, config: int = 1):
     """The three profiler runs, each started in /tmp with TMPDIR=/tmp and
     $REPO set to the repository root; the trace run's stdout (the benchmark's
@@ -106,6 +122,30 @@ def summarize(trace_dir, fetch_dir, write_dir, kernel_key, name, workload, algor
               f"| traffic / algorithmic | {(fetch_b + write_b) / algorithmic_bytes:.3f} |",
               f"| avg duration | {avg_ns / 1e3:.1f} us |",
               f"| achieved (algorithmic / duration) | {algorithmic_bytes / avg_ns:,.1f} GB/s |", ""]
+    sq = {}
+    for k in range(len(SQ_SETS)):
+        d = os.path.join(os.path.dirname(trace_dir), f"pmc_sq{k}")
+        if os.path.isdir(d):
+            with open(_find(d, "_counter_collection.csv")) as f:
+                for r in csv.DictReader(f):
+                    if kernel_key in r["Kernel_Name"]:
+                        sq.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    if sq:
+        m = {k: statistics.mean(v) for k, v in sq.items()}
+        g = lambda k: m.get(k, float("nan"))
+        lines += ["## Issue and stall counters of the dominant kernel (SQ, per dispatch)", "",
+                  "Commands:", ""] + [f"    {c}" for c in sq_commands()] + ["", "| counter | value |", "|---|---|"]
+        lines += [f"| {k} | {v:.4g} |" for k, v in sorted(m.items())]
+        lines += ["", "| derived | value |", "|---|---|",
+                  f"| wave cycles waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES) | {g('SQ_WAIT_ANY') / g('SQ_WAVE_CYCLES'):.3f} |",
+                  f"| wave cycles issuing (SQ_ACTIVE_INST_ANY / SQ_WAVE_CYCLES) | "
+                  f"{g('SQ_ACTIVE_INST_ANY') / g('SQ_WAVE_CYCLES'):.3f} |",
+                  f"| active lanes per VALU instruction (SQ_THREAD_CYCLES_VALU / SQ_ACTIVE_INST_VALU) | "
+                  f"{g('SQ_THREAD_CYCLES_VALU') / g('SQ_ACTIVE_INST_VALU'):.1f} of 64 |",
+                  f"| VALU instructions per event-batch launch | {g('SQ_INSTS_VALU'):.4g} |",
+                  f"| FP64 add+mul+fma share of VALU | "
+                  f"{(g('SQ_INSTS_VALU_ADD_F64') + g('SQ_INSTS_VALU_MUL_F64') + g('SQ_INSTS_VALU_FMA_F64')) / g('SQ_INSTS_VALU'):.3f} |",
+                  ""]
     os.makedirs(out_dir, exist_ok=True)
     with open(os.path.join(out_dir, f"{name}.md"), "w") as f:
         f.write("\n".join(lines))
