@@ -25,6 +25,10 @@
  *   O8  track state at the UT midpoint and q/p from the kink
  *   O9  ghost-killer feed-forward network and the "response < threshold"
  *       filter ("Ghost-Killer Neural Network", "Ghost Rejection")
+ *   O3' Dv1 instead of O3 ("Algorithm Design", the improved version): no
+ *       momentum window in UTbX; every UTbX hit in a Y sector compatible with
+ *       the seed forms, with the magnet point, a line that must meet a UTaX
+ *       hit (the axial triplet); stereo hits are added as in Dv0
  *   O10 two-track vertexing: trajectories of eq. 4 with gamma from eq. 3,
  *       Newton-Raphson point of closest approach, opposite charges, DOCA cut
  *       ("Vertexing Two Downstream Tracks", "Expected Physics Impact")
@@ -56,6 +60,11 @@ typedef struct {
     double gamma_c0, gamma_c1, fringe_polarity;
     int newton_iters;
     double doca_max;
+    /* Dv1: algorithm 1 selects the triplet search; hits carry a Y sector
+     * k = floor((y - sector_y0) / sector_h) in [0, n_sectors) */
+    int algorithm;
+    int n_sectors;
+    double sector_y0, sector_h, sector_tol;
 } orc_geom;
 
 /* ---------------------------------------------------------------- O2 ---- */
@@ -100,13 +109,15 @@ typedef struct {
 
 /* All hits of one layer whose x_hat = u + y*tan(alpha) lies within W of the
  * centre (inclusive), ordered by (|delta|, u, index) and cut to `cap`.  A
- * full scan: no sorting of the hits, no binary search. */
-static int window(const double *u, int n, double y, double tana, double centre, double W, int cap,
-                  win_hit *out, win_hit *scratch, fragility *fr)
+ * full scan: no sorting of the hits, no binary search.  With `sec` given,
+ * only hits whose Y sector lies in [klo, khi] are looked at. */
+static int window(const double *u, const int *sec, int klo, int khi, int n, double y, double tana, double centre,
+                  double W, int cap, win_hit *out, win_hit *scratch, fragility *fr)
 {
     if (cap <= 0) return 0;
     int m = 0;
     for (int i = 0; i < n; ++i) {
+        if (sec && (sec[i] < klo || sec[i] > khi)) continue;
         double xhat = u[i] + y * tana;
         double d = fabs(xhat - centre);
         double margin = fabs(d - W);
@@ -169,9 +180,14 @@ typedef struct {
 /* Enumerate every candidate of one seed in rank order (O3-O6).  `u[L]` is the
  * hit run of layer L (n[L] hits).  Returns the number of candidates written
  * (at most max_out), and the number that would have been written in *total. */
-static int enumerate_candidates(const orc_geom *g, const double *s, const double *const *u, const int *n,
-                                cand_t *out, int max_out, int *total, fragility *fr, win_hit *scratch)
+static int enumerate_dv1(const orc_geom *g, const double *s, const double *const *u, const int *const *sec,
+                         const int *n, cand_t *out, int max_out, int *total, fragility *fr, win_hit *scratch);
+
+static int enumerate_candidates(const orc_geom *g, const double *s, const double *const *u,
+                                const int *const *sec, const int *n, cand_t *out, int max_out, int *total,
+                                fragility *fr, win_hit *scratch)
 {
+    if (g->algorithm == 1) return enumerate_dv1(g, s, u, sec, n, out, max_out, total, fr, scratch);
     double xb[4], yL[4], xm;
     orc_extrapolate(g, s, xb, yL, &xm);
     double aq = fabs(s[4]);
@@ -179,7 +195,7 @@ static int enumerate_candidates(const orc_geom *g, const double *s, const double
     double W2 = g->w2_c0 + g->w2_c1 * aq;
     int cap3 = g->max_l3;
     win_hit *A3 = (win_hit *)malloc(sizeof(win_hit) * (size_t)(cap3 > 0 ? cap3 : 1));
-    int n3 = window(u[3], n[3], yL[3], g->tan_stereo[3], xb[3], W1, cap3, A3, scratch, fr);
+    int n3 = window(u[3], NULL, 0, 0, n[3], yL[3], g->tan_stereo[3], xb[3], W1, cap3, A3, scratch, fr);
     int nw[3];
     for (int L = 0; L < 3; ++L) nw[L] = g->n_closest[L] > 0 ? g->n_closest[L] : 1;
     int cnt = 0;
@@ -191,7 +207,7 @@ static int enumerate_candidates(const orc_geom *g, const double *s, const double
         for (int L = 0; L < 3; ++L) {
             double xr = xh3 + tprime * (g->z_layer[L] - g->z_layer[3]);
             int cap = g->n_closest[L] < 64 ? g->n_closest[L] : 64;
-            nA[L] = window(u[L], n[L], yL[L], g->tan_stereo[L], xr, W2, cap, AL[L], scratch, fr);
+            nA[L] = window(u[L], NULL, 0, 0, n[L], yL[L], g->tan_stereo[L], xr, W2, cap, AL[L], scratch, fr);
         }
         /* option lists: the ranked window hits, or {none} if the window is empty */
         int no[3];
@@ -227,6 +243,93 @@ static int enumerate_candidates(const orc_geom *g, const double *s, const double
     return cnt < max_out ? cnt : max_out;
 }
 
+/* Y sectors compatible with height y: the sectors k whose band
+ * [y0 + k h, y0 + (k + 1) h) overlaps [y - tol, y + tol] (y is a straight
+ * line: no field component bends it); klo > khi when none does.  The
+ * distance of y -/+ tol to the nearest sector boundary goes to the edge
+ * margin. */
+static void sector_range(const orc_geom *g, double y, int *klo, int *khi, fragility *fr)
+{
+    double a = (y - g->sector_tol - g->sector_y0) / g->sector_h;
+    double b = (y + g->sector_tol - g->sector_y0) / g->sector_h;
+    double ma = fabs(a - floor(a + 0.5)) * g->sector_h, mb = fabs(b - floor(b + 0.5)) * g->sector_h;
+    if (ma < fr->edge_margin) fr->edge_margin = ma;
+    if (mb < fr->edge_margin) fr->edge_margin = mb;
+    double fa = floor(a), fb = floor(b);
+    double top = (double)(g->n_sectors - 1);
+    /* outside every band: an empty range */
+    if (fb < 0.0 || fa > top) {
+        *klo = 1;
+        *khi = 0;
+        return;
+    }
+    *klo = (int)(fa < 0.0 ? 0.0 : fa);
+    *khi = (int)(fb > top ? top : fb);
+}
+
+/* Dv1 (O3'): candidates of one seed from axial triplets.  Every UTbX hit of
+ * a compatible Y sector, in index order (no momentum window), defines with
+ * the magnet point a straight line; the line's refined windows in UTaX, UTaU
+ * and UTbV are those of Dv0 restricted to compatible sectors.  A triplet
+ * needs a UTaX hit; the stereo options and the fit follow Dv0.  Candidate
+ * index: ((i3 * nw0 + i0) * nw1 + i1) * nw2 + i2, i3 the UTbX hit's index in
+ * its layer run.  With sec == NULL every hit counts as compatible. */
+static int enumerate_dv1(const orc_geom *g, const double *s, const double *const *u, const int *const *sec,
+                         const int *n, cand_t *out, int max_out, int *total, fragility *fr, win_hit *scratch)
+{
+    double xb[4], yL[4], xm;
+    orc_extrapolate(g, s, xb, yL, &xm);
+    double W2 = g->w2_c0 + g->w2_c1 * fabs(s[4]);
+    int klo[4] = {0, 0, 0, 0}, khi[4] = {0, 0, 0, 0};
+    for (int L = 0; L < 4; ++L)
+        if (sec) sector_range(g, yL[L], &klo[L], &khi[L], fr);
+    int nw[3];
+    for (int L = 0; L < 3; ++L) nw[L] = g->n_closest[L] > 0 ? g->n_closest[L] : 1;
+    int cnt = 0;
+    win_hit AL[3][64];
+    for (int i3 = 0; i3 < n[3]; ++i3) {
+        if (sec && (sec[3][i3] < klo[3] || sec[3][i3] > khi[3])) continue;
+        double xh3 = u[3][i3] + yL[3] * g->tan_stereo[3];
+        double tprime = (xm - xh3) / (g->z_magnet - g->z_layer[3]);
+        int nA[3];
+        for (int L = 0; L < 3; ++L) {
+            double xr = xh3 + tprime * (g->z_layer[L] - g->z_layer[3]);
+            int cap = g->n_closest[L] < 64 ? g->n_closest[L] : 64;
+            nA[L] = window(u[L], sec ? sec[L] : NULL, klo[L], khi[L], n[L], yL[L], g->tan_stereo[L], xr, W2, cap,
+                           AL[L], scratch, fr);
+        }
+        if (nA[0] == 0) continue; /* no axial triplet */
+        int no[3];
+        for (int L = 0; L < 3; ++L) no[L] = nA[L] > 0 ? nA[L] : 1;
+        for (int i0 = 0; i0 < no[0]; ++i0)
+            for (int i1 = 0; i1 < no[1]; ++i1)
+                for (int i2 = 0; i2 < no[2]; ++i2) {
+                    cand_t cd;
+                    cd.c = ((i3 * nw[0] + i0) * nw[1] + i1) * nw[2] + i2;
+                    cd.hit[3] = i3;
+                    cd.hit[0] = AL[0][i0].idx;
+                    cd.hit[1] = nA[1] > 0 ? AL[1][i1].idx : -1;
+                    cd.hit[2] = nA[2] > 0 ? AL[2][i2].idx : -1;
+                    double dz[4], xx[4];
+                    int k = 0;
+                    for (int L = 0; L < 4; ++L) {
+                        if (cd.hit[L] < 0) continue;
+                        dz[k] = g->z_layer[L] - g->z_ref;
+                        xx[k] = u[L][cd.hit[L]] + yL[L] * g->tan_stereo[L];
+                        ++k;
+                    }
+                    cd.nhits = k;
+                    cd.valid = k >= 3; /* UTaX is present in every triplet */
+                    cd.a = cd.b = cd.chi2 = 0.0;
+                    orc_fit(k, dz, xx, g->sigma_hit, &cd.a, &cd.b, &cd.chi2);
+                    if (cnt < max_out) out[cnt] = cd;
+                    ++cnt;
+                }
+    }
+    *total = cnt;
+    return cnt < max_out ? cnt : max_out;
+}
+
 /* lexicographic (more hits, lower chi2, lower candidate index) */
 static int better(const cand_t *x, const cand_t *y)
 {
@@ -237,17 +340,19 @@ static int better(const cand_t *x, const cand_t *y)
 
 /* Candidate list of one seed, for brute-force comparisons in the tests. */
 int orc_candidates(const orc_geom *g, const double *s, const double *u0, int n0, const double *u1, int n1,
-                   const double *u2, int n2, const double *u3, int n3, int max_out, int *c_out, int *hits_out,
-                   int *nhits_out, int *valid_out, double *a_out, double *b_out, double *chi2_out)
+                   const double *u2, int n2, const double *u3, int n3, const int *sec0, const int *sec1,
+                   const int *sec2, const int *sec3, int max_out, int *c_out, int *hits_out, int *nhits_out,
+                   int *valid_out, double *a_out, double *b_out, double *chi2_out)
 {
     const double *u[4] = {u0, u1, u2, u3};
+    const int *sec[4] = {sec0, sec1, sec2, sec3};
     int n[4] = {n0, n1, n2, n3};
     int big = n0 + n1 + n2 + n3 + 1;
     win_hit *scratch = (win_hit *)malloc(sizeof(win_hit) * (size_t)big);
     cand_t *cands = (cand_t *)malloc(sizeof(cand_t) * (size_t)(max_out > 0 ? max_out : 1));
     fragility fr = {INFINITY, INFINITY};
     int total = 0;
-    int m = enumerate_candidates(g, s, u, n, cands, max_out, &total, &fr, scratch);
+    int m = enumerate_candidates(g, s, u, sec0 ? sec : NULL, n, cands, max_out, &total, &fr, scratch);
     for (int i = 0; i < m; ++i) {
         c_out[i] = cands[i].c;
         for (int L = 0; L < 4; ++L) hits_out[4 * i + L] = cands[i].hit[L];
@@ -269,6 +374,7 @@ typedef struct {
     const double *sx, *sy, *stx, *sty, *sqop;
     const int *hit_off;
     const double *hu;
+    const int *hsec; /* Y sector per hit (Dv1), may be NULL */
     /* outputs per seed */
     double *x, *y, *tx, *ty, *qop, *chi2;
     int *nhits, *hits, *cand;
@@ -303,18 +409,25 @@ static void *track_worker(void *arg)
         for (int L = 0; L < 3; ++L) per3 *= (g->n_closest[L] > 0 ? g->n_closest[L] : 1);
         maxc = (g->max_l3 > 0 ? g->max_l3 : 1) * per3;
     }
+    int per3 = maxc / (g->max_l3 > 0 ? g->max_l3 : 1);
     cand_t *cands = (cand_t *)malloc(sizeof(cand_t) * (size_t)maxc);
     size_t scratch_n = 16;
     win_hit *scratch = (win_hit *)malloc(sizeof(win_hit) * scratch_n);
     for (int e = J->e_begin; e < J->e_end; ++e) {
         int s0 = J->seed_off[e], s1 = J->seed_off[e + 1];
         const double *u[4];
+        const int *sec[4] = {NULL, NULL, NULL, NULL};
         int n[4];
         int tot = 0;
         for (int L = 0; L < 4; ++L) {
             u[L] = J->hu + J->hit_off[4 * e + L];
+            if (J->hsec) sec[L] = J->hsec + J->hit_off[4 * e + L];
             n[L] = J->hit_off[4 * e + L + 1] - J->hit_off[4 * e + L];
             tot += n[L];
+        }
+        if (g->algorithm == 1 && n[3] * per3 > maxc) { /* Dv1: every UTbX hit may open candidates */
+            maxc = n[3] * per3;
+            cands = (cand_t *)realloc(cands, sizeof(cand_t) * (size_t)maxc);
         }
         if ((size_t)tot + 1 > scratch_n) {
             scratch_n = (size_t)tot + 1;
@@ -328,7 +441,7 @@ static void *track_worker(void *arg)
             if (!event_ok || !all_finite(s, 5)) continue;
             fragility fr = {INFINITY, INFINITY};
             int total = 0;
-            int m = enumerate_candidates(g, s, u, n, cands, maxc, &total, &fr, scratch);
+            int m = enumerate_candidates(g, s, u, J->hsec ? sec : NULL, n, cands, maxc, &total, &fr, scratch);
             int best = -1;
             for (int k = 0; k < m; ++k) {
                 if (!cands[k].valid) continue;
@@ -370,7 +483,7 @@ static void *track_worker(void *arg)
  * same number of hits), rank_gap (|delta| gap at a rank cut). */
 int orc_find_tracks(const orc_geom *g, int n_events, const int *seed_off, const double *sx, const double *sy,
                     const double *stx, const double *sty, const double *sqop, const int *hit_off, const double *hu,
-                    double *x, double *y, double *tx, double *ty, double *qop, double *chi2, int *nhits, int *hits,
+                    const int *hit_sector, double *x, double *y, double *tx, double *ty, double *qop, double *chi2, int *nhits, int *hits,
                     int *cand, double *edge_margin, double *chi2_gap, double *rank_gap, int n_threads)
 {
     if (n_threads < 1) n_threads = 1;
@@ -380,7 +493,8 @@ int orc_find_tracks(const orc_geom *g, int n_events, const int *seed_off, const 
     track_job jobs[256];
     for (int t = 0; t < n_threads; ++t) {
         track_job J = {g, (int)((long)n_events * t / n_threads), (int)((long)n_events * (t + 1) / n_threads),
-                       seed_off, sx, sy, stx, sty, sqop, hit_off, hu, x, y, tx, ty, qop, chi2, nhits, hits, cand,
+                       seed_off, sx, sy, stx, sty, sqop, hit_off, hu, hit_sector, x, y, tx, ty, qop, chi2, nhits,
+                       hits, cand,
                        edge_margin, chi2_gap, rank_gap};
         jobs[t] = J;
     }
@@ -535,6 +649,10 @@ int orc_score_candidates(const orc_geom *g, int n_events, const int *seed_off, c
                          int *row_hits, int *row_nhits, double *row_state /* [6]: x y tx ty qop chi2 (f32) */,
                          double *row_score)
 {
+    /* candidate rows follow Dv0's enumeration */
+    orc_geom g0 = *g;
+    g0.algorithm = 0;
+    g = &g0;
     int per3 = 1;
     for (int L = 0; L < 3; ++L) per3 *= (g->n_closest[L] > 0 ? g->n_closest[L] : 1);
     int maxc = (g->max_l3 > 0 ? g->max_l3 : 1) * per3;
@@ -555,7 +673,7 @@ int orc_score_candidates(const orc_geom *g, int n_events, const int *seed_off, c
             if (!all_finite(s, 5)) continue;
             fragility fr = {INFINITY, INFINITY};
             int total = 0;
-            int m = enumerate_candidates(g, s, u, n, cands, maxc, &total, &fr, scratch);
+            int m = enumerate_candidates(g, s, u, NULL, n, cands, maxc, &total, &fr, scratch);
             for (int k = 0; k < m; ++k) {
                 const cand_t *cd = &cands[k];
                 if (!cd->valid) continue;

@@ -34,6 +34,9 @@ class OrcGeom(C.Structure):
         ("gamma_c0", C.c_double), ("gamma_c1", C.c_double), ("fringe_polarity", C.c_double),
         ("newton_iters", C.c_int),
         ("doca_max", C.c_double),
+        ("algorithm", C.c_int),
+        ("n_sectors", C.c_int),
+        ("sector_y0", C.c_double), ("sector_h", C.c_double), ("sector_tol", C.c_double),
     ]
 
 
@@ -47,6 +50,10 @@ def make_geom(g: dict) -> OrcGeom:
     o.max_l3 = int(g["max_l3"])
     o.n_closest[:] = [int(v) for v in g["n_closest"]]
     o.newton_iters = int(g["newton_iters"])
+    o.algorithm = int(g.get("algorithm", 0))
+    o.n_sectors = int(g.get("n_sectors", 1))
+    for k, d in (("sector_y0", -700.0), ("sector_h", 1400.0), ("sector_tol", 0.0)):
+        setattr(o, k, float(g.get(k, d)))
     return o
 
 
@@ -98,13 +105,15 @@ def find_tracks(batch, g: dict, n_threads: int = 1, float64_truth: bool = False)
     hu_a, hu_p = _d(hu)
     so_a, so_p = _i(batch.seed_off)
     ho_a, ho_p = _i(batch.hit_off)
+    sec = getattr(batch, "hit_sector", None)
+    sec_a, sec_p = _i(sec) if sec is not None else (None, None)
     out = {k: np.zeros(S, np.float64) for k in ("x", "y", "tx", "ty", "qop", "chi2", "edge_margin",
                                                   "chi2_gap", "rank_gap")}
     out["nhits"] = np.zeros(S, np.int32)
     out["hits"] = np.zeros((S, 4), np.int32)
     out["cand"] = np.zeros(S, np.int32)
     geom = make_geom(g)
-    L.orc_find_tracks(C.byref(geom), C.c_int(batch.n_events), so_p, *cols, ho_p, hu_p,
+    L.orc_find_tracks(C.byref(geom), C.c_int(batch.n_events), so_p, *cols, ho_p, hu_p, sec_p,
                       *[out[k].ctypes.data_as(_dp) for k in ("x", "y", "tx", "ty", "qop", "chi2")],
                       out["nhits"].ctypes.data_as(_ip), out["hits"].ctypes.data_as(_ip),
                       out["cand"].ctypes.data_as(_ip),
@@ -278,8 +287,9 @@ def fit(dz, x, sigma):
     return a.value, b.value, c2.value
 
 
-def candidates(g: dict, seed, layers, max_out: int = 4096) -> dict:
-    """Every enumerated candidate of one seed, in enumeration order."""
+def candidates(g: dict, seed, layers, max_out: int = 4096, sectors=None) -> dict:
+    """Every enumerated candidate of one seed, in enumeration order
+    (``sectors``: optional per-layer Y-sector ids of the hits, Dv1)."""
     L = lib()
     keep = []
     args = []
@@ -287,6 +297,13 @@ def candidates(g: dict, seed, layers, max_out: int = 4096) -> dict:
         a, p = _d(np.asarray(layers[l], dtype=np.float64))
         keep.append(a)
         args += [p, C.c_int(len(a))]
+    for l in range(4):
+        if sectors is None:
+            args.append(None)
+        else:
+            a, p = _i(np.asarray(sectors[l], dtype=np.int32))
+            keep.append(a)
+            args.append(p)
     s, sp = _d(seed)
     c = np.zeros(max_out, np.int32)
     hits = np.zeros((max_out, 4), np.int32)

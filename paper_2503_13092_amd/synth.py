@@ -29,6 +29,9 @@ these seeded events stand in for them):
 * Hits: true hits at layers downstream of the decay with N(0, 0.05) mm
   smear; noise hits uniform over |x| < 800, |y| < 700 mm; hits shuffled
   within each (event, layer) run, seeds shuffled within each event.
+* Y sectors: every hit also carries the 100 mm band of its layer that its
+  true y falls in (14 bands over |y| < 700 mm); Dv1's triplet search uses
+  them.  They are computed from the generated y, with no extra random draw.
 
 Draw order (numpy PCG64, ``default_rng(seed)``): occupancies -> LLPs ->
 daughter charges/momenta/slopes (with rejection redraws) -> ghost kinematics
@@ -49,6 +52,8 @@ UT_XMAX = 800.0
 UT_YMAX = 700.0
 SEED_XMAX = 3000.0
 SEED_YMAX = 2500.0
+# Y sectors: horizontal bands of a UT layer, 100 mm high (about one sensor)
+N_SECTORS = 14
 
 
 def default_geometry(loose: bool = False) -> Dict:
@@ -80,6 +85,9 @@ def default_geometry(loose: bool = False) -> Dict:
         u_min=-(UT_XMAX + UT_YMAX * TAN5),
         u_max=(UT_XMAX + UT_YMAX * TAN5),
         clone_kill=0,
+        # Dv1 (triplet search): UT hits grouped into Y sectors of their layer
+        algorithm=0,
+        n_sectors=N_SECTORS, sector_y0=-UT_YMAX, sector_h=2.0 * UT_YMAX / N_SECTORS, sector_tol=5.0,
     )
     if loose:
         g.update(w1_c0=100.0, w1_c1=0.0, w2_c0=10.0, w2_c1=0.0)
@@ -130,6 +138,7 @@ class EventBatch:
     hit_off: np.ndarray       # int32 [4E+1]
     hu: np.ndarray            # float32 [H]
     truth: Dict[str, np.ndarray] = dataclasses.field(default_factory=dict)
+    hit_sector: Optional[np.ndarray] = None   # uint8 [H]: Y sector of each hit (Dv1)
 
     @property
     def n_seeds(self) -> int:
@@ -169,30 +178,44 @@ class EventBatch:
             elif k.startswith("hit_") and len(v) == self.n_hits:
                 truth[k] = v[h_idx]
         return EventBatch(len(events), seed_off, self.sx[s_idx], self.sy[s_idx], self.stx[s_idx],
-                          self.sty[s_idx], self.sqop[s_idx], hit_off, self.hu[h_idx], truth)
+                          self.sty[s_idx], self.sqop[s_idx], hit_off, self.hu[h_idx], truth,
+                          None if self.hit_sector is None else self.hit_sector[h_idx])
 
 
 def batch_from_lists(events, dtype=np.float32) -> EventBatch:
     """Build a batch from explicit per-event content.
 
     ``events`` is a list of dicts with ``seeds`` (list of (x, y, tx, ty, qop))
-    and ``hits`` (list of 4 lists of u).  Used for hand-built test events.
+    and ``hits`` (list of 4 lists of u), optionally ``sectors`` (4 lists of
+    Y-sector ids, default 0).  Used for hand-built test events.
     """
     seed_off, hit_off = [0], [0]
     cols = [[] for _ in range(5)]
-    hu = []
+    hu, sec = [], []
     for ev in events:
         for s in ev.get("seeds", []):
             for k in range(5):
                 cols[k].append(s[k])
         seed_off.append(seed_off[-1] + len(ev.get("seeds", [])))
         layers = ev.get("hits", [[], [], [], []])
+        secs = ev.get("sectors", [[0] * len(h) for h in layers])
         for l in range(4):
             hu.extend(layers[l])
+            sec.extend(secs[l])
             hit_off.append(hit_off[-1] + len(layers[l]))
     arr = [np.asarray(c, dtype=dtype) for c in cols]
     return EventBatch(len(events), np.asarray(seed_off, np.int32), *arr,
-                      np.asarray(hit_off, np.int32), np.asarray(hu, dtype=dtype))
+                      np.asarray(hit_off, np.int32), np.asarray(hu, dtype=dtype),
+                      hit_sector=np.asarray(sec, dtype=np.uint8))
+
+
+def sector_of(y, g: Optional[Dict] = None) -> np.ndarray:
+    """Y sector of points at height y (the band a hit's sensor covers)."""
+    d = default_geometry()
+    g = g or d
+    y0, h, n = (g.get(k, d[k]) for k in ("sector_y0", "sector_h", "n_sectors"))
+    k = np.floor((np.asarray(y, dtype=np.float64) - y0) / h)
+    return np.clip(k, 0, n - 1).astype(np.uint8)
 
 
 def _log_uniform(rng, lo, hi, n):
@@ -324,7 +347,7 @@ def generate(config=1, n_events: Optional[int] = None, seed: Optional[int] = Non
 
     # 6. true hits (true daughters only, layers downstream of the decay)
     tr_idx = np.nonzero(T_true)[0]
-    th_track, th_layer, th_u = [], [], []
+    th_track, th_layer, th_u, th_y = [], [], [], []
     for L in range(4):
         down = tr_idx[zl[L] > T_z[tr_idx]]
         xL = T_vx[down] + T_txb[down] * (zl[L] - T_z[down])
@@ -333,14 +356,16 @@ def generate(config=1, n_events: Optional[int] = None, seed: Optional[int] = Non
         th_track.append(down)
         th_layer.append(np.full(len(down), L))
         th_u.append(u)
+        th_y.append(yL)
     th_track = np.concatenate(th_track)
     th_layer = np.concatenate(th_layer)
     th_u = np.concatenate(th_u)
+    th_y = np.concatenate(th_y)
     if smear:
         th_u = th_u + rng.normal(0.0, g["sigma_hit"], len(th_u))
     if hit_efficiency < 1.0:
         keep = rng.uniform(0.0, 1.0, len(th_u)) < hit_efficiency
-        th_track, th_layer, th_u = th_track[keep], th_layer[keep], th_u[keep]
+        th_track, th_layer, th_u, th_y = th_track[keep], th_layer[keep], th_u[keep], th_y[keep]
     th_ev = T_ev[th_track]
 
     # 7. noise hits
@@ -358,10 +383,12 @@ def generate(config=1, n_events: Optional[int] = None, seed: Optional[int] = Non
     # 8. grouping + shuffles
     all_grp = np.concatenate([th_ev * 4 + th_layer, nz_grp])
     all_u = np.concatenate([th_u, nu_])
+    all_y = np.concatenate([th_y, ny])
     all_owner_track = np.concatenate([th_track, np.full(NN, -1)])
     hkey = rng.integers(0, 1 << 31, len(all_u), dtype=np.int64)
     horder = np.argsort(all_grp.astype(np.int64) << 31 | hkey, kind="stable")
     all_grp, all_u, all_owner_track = all_grp[horder], all_u[horder], all_owner_track[horder]
+    all_y = all_y[horder]
     counts = np.bincount(all_grp, minlength=4 * E)
     hit_off = np.zeros(4 * E + 1, np.int64)
     hit_off[1:] = np.cumsum(counts)
@@ -386,7 +413,7 @@ def generate(config=1, n_events: Optional[int] = None, seed: Optional[int] = Non
     f32 = np.float32
     return EventBatch(E, seed_off.astype(np.int32), sx[sorder].astype(f32), sy[sorder].astype(f32),
                       stx[sorder].astype(f32), sty[sorder].astype(f32), sqop[sorder].astype(f32),
-                      hit_off.astype(np.int32), all_u.astype(f32), truth)
+                      hit_off.astype(np.int32), all_u.astype(f32), truth, sector_of(all_y, g))
 
 
 def vertex_track_sample(n_events: int, n_pairs: int, n_random: int, seed: int = 7,
