@@ -144,6 +144,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-copy-ceiling", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-dv1", action="store_true", help="skip the Dv1 (triplet search) line")
     ap.add_argument("--serve-seconds", type=float, default=1.5)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -230,7 +231,7 @@ def main():
     traffic = stored_traffic("k_track_fused", src_hash)
     roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 5), traffic=traffic,
-                    kernel="k_track<256,false,true>: hit staging, search, fit, ghost-killer MLP and vertexing fused",
+                    kernel="k_track<256,false,true,false>: hit staging, search, fit, ghost-killer MLP and vertexing fused",
                     kernel_ms=round(fused_ms, 4), algorithmic_bytes_per_launch=round(step_bytes))
     vertex_info = dict(kept_tracks=kept, vertices=n_vtx, unfused_track_ms=round(trk_ms, 4),
                        unfused_vertex_ms=round(vtx_ms, 4), unfused_vertex_algorithmic_bytes=round(vb))
@@ -257,6 +258,31 @@ def main():
         pdt = float(np.mean(pe))
         out["plain"] = dict(events_per_s=round(E / pdt, 1), ms_per_step=round(pdt * 1e3, 3),
                             launches_per_step=2 * E, speedup_of_persistent=round(value / (E / pdt), 2))
+    if not args.no_dv1:
+        # the same batch under Dv1 (triplet search, Y sectors), same launch
+        g1 = dict(g, algorithm=1)
+        ctx1 = ds.Context(0, g1, w)
+        for k in range(args.warmup):
+            ev, tr, vt = copies[k % len(copies)]
+            ds.ds_process(ctx1.handle, ev, tr, vt, mode, score_max=score_max, stream=stream)
+        torch.cuda.synchronize()
+        ev_pairs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+        t1 = time.perf_counter()
+        for k in range(args.steps):
+            ev, tr, vt = copies[k % len(copies)]
+            ev_pairs[k][0].record(stream)
+            ds.ds_process(ctx1.handle, ev, tr, vt, mode, score_max=score_max, stream=stream)
+            ev_pairs[k][1].record(stream)
+        torch.cuda.synchronize()
+        d1 = time.perf_counter() - t1
+        ms1 = float(np.mean([e[0].elapsed_time(e[1]) for e in ev_pairs]))
+        ev, tr, vt = copies[(args.steps - 1) % len(copies)]
+        nh1 = tr.nhits.cpu().numpy()
+        out["dv1"] = dict(events_per_s=round(E * args.steps / d1, 1), kernel_ms=round(ms1, 4),
+                          tracks=int(np.sum(nh1 > 0)), vertices=int(vt.count.sum().item()),
+                          flags=int(tr.flags.item()) | int(vt.flags.item()),
+                          launch="ds_process, algorithm 1: one fused persistent launch, hipGraph replay")
+        ctx1.close()
     if not args.no_copy_ceiling:
         cc = copy_ceiling_gbs(torch)
         out["roofline"]["copy_ceiling_GBs"] = round(cc, 1)

@@ -90,6 +90,23 @@ enum {
  *                        ("Ghost Rejection"); used by ds_process.
  *  clone_kill          : nonzero: ds_process kills clones (ds_kill_clones)
  *                        between track finding and the ghost-killer.
+ *  algorithm           : 0 = Dv0 (momentum window in UTbX, up to max_l3
+ *                        closest hits); 1 = Dv1, the improved version of
+ *                        "Algorithm Design": no momentum window, every UTbX
+ *                        hit of a compatible Y sector is joined to the magnet
+ *                        point and the line must meet a UTaX hit (the axial
+ *                        triplet); stereo hits, fit and selection as in Dv0.
+ *                        Dv1 needs ds_events.hit_sector.  Candidate rows
+ *                        (ds_score_candidates) always follow Dv0.
+ *  n_sectors, sector_y0,
+ *  sector_h, sector_tol: Dv1 Y sectors: sector k of a layer is the band
+ *                        [sector_y0 + k*sector_h, sector_y0 + (k+1)*sector_h),
+ *                        k < n_sectors (<= 15).  A seed reaches the sectors
+ *                        that overlap [y - sector_tol, y + sector_tol], y its
+ *                        straight-line height at the layer;
+ *                        2*sector_tol < sector_h.  Ignored when algorithm = 0.
+ *                        Dv1 candidate index: ((i3*nw0 + i0)*nw1 + i1)*nw2 + i2
+ *                        with i3 the UTbX hit's index in its layer run.
  */
 typedef struct {
     double z_layer[4];
@@ -106,6 +123,9 @@ typedef struct {
     double doca_max;
     double ghost_threshold;
     int32_t clone_kill;
+    int32_t algorithm;
+    int32_t n_sectors;
+    double sector_y0, sector_h, sector_tol;
 } ds_geometry;
 
 /*
@@ -120,6 +140,8 @@ typedef struct {
  *  max_hits_per_event        : caller's upper bounds (all four layers for hits);
  *                              they size on-chip buffers.  An event above a
  *                              bound is flagged DS_F_CAPACITY and skipped.
+ *  hit_sector [n_hits]       : Y sector of each hit (Dv1; nullable for Dv0).
+ *                              A sector id >= n_sectors is never compatible.
  */
 typedef struct {
     int32_t n_events;
@@ -131,6 +153,7 @@ typedef struct {
     const float *sx, *sy, *stx, *sty, *sqop;
     const int32_t *hit_off;
     const float *hu;
+    const uint8_t *hit_sector;
 } ds_events;
 
 /*
@@ -214,8 +237,10 @@ ds_status ds_load_geometry(ds_ctx *ctx, const ds_geometry *g, const float *mlp_w
 ds_status ds_load_lines(ds_ctx *ctx, const float *line_weights, size_t n_weights);
 
 /*
- * Track finding ("The Downstream Algorithm", Dv0): one track slot per seed.
+ * Track finding ("The Downstream Algorithm", Dv0, or Dv1's triplet search when
+ * the loaded geometry says algorithm = 1): one track slot per seed.
  * mode = DS_MODE_*; fuse_mlp != 0 also writes the ghost-killer score.
+ * DS_E_ARG if Dv1 is loaded and ev->hit_sector is null.
  */
 ds_status ds_find_tracks(ds_ctx *ctx, const ds_events *ev, const ds_tracks *out, int mode, int fuse_mlp,
                          void *hip_stream);

@@ -45,6 +45,7 @@ struct ds_ctx {
     double u_min = -1000.0, u_max = 1000.0;
     double ghost_threshold = 0.5;
     bool clone_kill = false;
+    int algorithm = 0;             // 0: Dv0 window search, 1: Dv1 triplet search
     float *d_W = nullptr;
     float *d_WL = nullptr;   // trigger-line networks
     int *d_counters = nullptr;  // [MAX_STREAM_SLOTS][4]
@@ -137,12 +138,17 @@ void append_bytes(std::string &key, const K &v)
 template <int B>
 hipError_t launch_track_b(const ds::TrackArgs &a, const ds::DevGeom &G, int grid, size_t lds, hipStream_t s)
 {
+    const ds::TrackKernArgs k{a, G};
     if (a.cmax > 0)
-        hipLaunchKernelGGL((ds::k_track<B, true, false>), dim3(grid), dim3(B), lds, s, ds::TrackKernArgs{a, G});
+        hipLaunchKernelGGL((ds::k_track<B, true, false, false>), dim3(grid), dim3(B), lds, s, k);
+    else if (a.hsec && a.vcount)
+        hipLaunchKernelGGL((ds::k_track<B, false, true, true>), dim3(grid), dim3(B), lds, s, k);
+    else if (a.hsec)
+        hipLaunchKernelGGL((ds::k_track<B, false, false, true>), dim3(grid), dim3(B), lds, s, k);
     else if (a.vcount)
-        hipLaunchKernelGGL((ds::k_track<B, false, true>), dim3(grid), dim3(B), lds, s, ds::TrackKernArgs{a, G});
+        hipLaunchKernelGGL((ds::k_track<B, false, true, false>), dim3(grid), dim3(B), lds, s, k);
     else
-        hipLaunchKernelGGL((ds::k_track<B, false, false>), dim3(grid), dim3(B), lds, s, ds::TrackKernArgs{a, G});
+        hipLaunchKernelGGL((ds::k_track<B, false, false, false>), dim3(grid), dim3(B), lds, s, k);
     return hipGetLastError();
 }
 
@@ -180,9 +186,11 @@ hipError_t set_kernel_attributes()
 {
     const void *fns[] = {
 #define DS_TRACK_FNS(B)                                                                                     \
-    reinterpret_cast<const void *>(&ds::k_track<B, false, false>),                                          \
-        reinterpret_cast<const void *>(&ds::k_track<B, true, false>),                                       \
-        reinterpret_cast<const void *>(&ds::k_track<B, false, true>)
+    reinterpret_cast<const void *>(&ds::k_track<B, false, false, false>),                                   \
+        reinterpret_cast<const void *>(&ds::k_track<B, true, false, false>),                                \
+        reinterpret_cast<const void *>(&ds::k_track<B, false, true, false>),                                \
+        reinterpret_cast<const void *>(&ds::k_track<B, false, false, true>),                                \
+        reinterpret_cast<const void *>(&ds::k_track<B, false, true, true>)
         DS_TRACK_FNS(64), DS_TRACK_FNS(128), DS_TRACK_FNS(256), DS_TRACK_FNS(512),
 #undef DS_TRACK_FNS
         reinterpret_cast<const void *>(&ds::k_vertex<64, VTX_PPT>),
@@ -211,9 +219,14 @@ struct VertexPlan {
 };
 
 ds_status plan_track(ds_ctx *c, const ds_events *ev, const ds_tracks *out, int fuse, int *counters, TrackPlan *p,
-                     bool vertex_fused = false)
+                     bool vertex_fused = false, bool cand_rows = false)
 {
-    const int nb = c->trk.bins;
+    // Dv1 buckets hits by (layer, Y sector, u bin) plus one bucket per layer
+    // for sector ids out of range; candidate rows always follow Dv0
+    const bool dv1 = c->algorithm == 1 && !cand_rows;
+    if (dv1 && !ev->hit_sector) return DS_E_ARG;
+    const int nbu = dv1 ? std::max(4, c->trk.bins / c->G.nsec) : c->trk.bins;
+    const int nb = dv1 ? c->G.nsec * nbu + 1 : nbu;
     int hcap = round_up(std::max(ev->max_hits_per_event, 1), 64);
     const int block = c->trk.block;
     // items per chunk: room for ITEMS_PER_SEED per seed; a chunk shrinks when its seeds need more
@@ -259,8 +272,10 @@ ds_status plan_track(ds_ctx *c, const ds_events *ev, const ds_tracks *out, int f
     a.icap = icap;
     a.tcap = tcap;
     a.nb = nb;
+    a.nbu = nbu;
     a.u0 = (float)c->u_min;
-    a.inv_bw = (float)((double)nb / (c->u_max - c->u_min));
+    a.inv_bw = (float)((double)nbu / (c->u_max - c->u_min));
+    a.hsec = dv1 ? ev->hit_sector : nullptr;
     p->block = block;
     p->grid = std::max(1, std::min(ev->n_events, c->n_cu * c->trk.wg_per_cu));
     p->lds = lds;
@@ -534,6 +549,13 @@ ds_status ds_load_geometry(ds_ctx *c, const ds_geometry *g, const float *w, size
     if (!(g->u_max > g->u_min) || !(g->sigma_hit > 0.0) || g->z_magnet == g->z_layer[3]) return DS_E_ARG;
     for (int L = 0; L < 3; ++L)
         if (!(g->z_layer[L] < g->z_layer[L + 1])) return DS_E_ARG;
+    if (g->algorithm != 0 && g->algorithm != 1) return DS_E_ARG;
+    // Dv1: at most 15 sectors (4-bit spans) and a tolerance band narrower than
+    // a sector, so that a seed is compatible with at most two of them
+    if (g->algorithm == 1 && (g->n_sectors < 1 || g->n_sectors > 15 || !(g->sector_h > 0.0) ||
+                              !(g->sector_tol >= 0.0) || !(2.0 * g->sector_tol < g->sector_h) ||
+                              !std::isfinite(g->sector_y0)))
+        return DS_E_ARG;
     std::lock_guard<std::mutex> lock(c->mu);
     if (hipSetDevice(c->device) != hipSuccess) return DS_E_DEVICE;
     ds::DevGeom G{};
@@ -581,6 +603,10 @@ ds_status ds_load_geometry(ds_ctx *c, const ds_geometry *g, const float *w, size
         G.nw[L] = std::max(g->n_closest[L], 1);
     }
     G.newton_iters = g->newton_iters;
+    G.nsec = g->algorithm == 1 ? g->n_sectors : 1;
+    G.sec_y0 = g->sector_y0;
+    G.sec_h = g->algorithm == 1 ? g->sector_h : 1.0;
+    G.sec_tol = g->sector_tol;
     if (!c->d_W && hipMalloc(&c->d_W, sizeof(float) * ds::NWEIGHTS) != hipSuccess) return DS_E_NOMEM;
     if (hipMemcpy(c->d_W, w, sizeof(float) * ds::NWEIGHTS, hipMemcpyHostToDevice) != hipSuccess)
         return DS_E_DEVICE;
@@ -589,6 +615,7 @@ ds_status ds_load_geometry(ds_ctx *c, const ds_geometry *g, const float *w, size
     c->u_max = g->u_max;
     c->ghost_threshold = g->ghost_threshold;
     c->clone_kill = g->clone_kill != 0;
+    c->algorithm = g->algorithm;
     // cached graphs hold the old geometry as kernel arguments
     for (auto &e : c->graphs) {
         (void)hipGraphExecDestroy(e.second.exec);
@@ -688,7 +715,7 @@ ds_status ds_score_candidates(ds_ctx *c, const ds_events *ev, const ds_candidate
     std::memset(&none, 0, sizeof(none));
     none.flags = out->flags;
     TrackPlan p;
-    st = plan_track(c, ev, &none, 0, counters, &p);
+    st = plan_track(c, ev, &none, 0, counters, &p, false, true);
     if (st != DS_OK) return st;
     p.a.cmax = cmax;
     p.a.r_seed = out->seed;

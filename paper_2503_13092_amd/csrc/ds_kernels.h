@@ -55,6 +55,9 @@ struct DevGeom {
     int ncl[3];
     int nw[3];                           // max(ncl, 1): radix of the candidate index
     int newton_iters;
+    // Dv1 Y sectors: band k = [sec_y0 + k sec_h, sec_y0 + (k + 1) sec_h), k < nsec
+    double sec_y0, sec_h, sec_tol;
+    int nsec;
 };
 
 struct TrackArgs {
@@ -84,8 +87,10 @@ struct TrackArgs {
     int *voverflow, *vflags;
     float *m_pipi, *m_ppi, *line0, *line1, *line2, *line3;
     const float *WL;
-    int nb;              // bins per layer
-    float u0, inv_bw;    // bin = floor((u - u0) * inv_bw), clamped
+    int nb;              // buckets per layer: u bins (Dv0) or sectors x u bins + 1 (Dv1)
+    int nbu;             // u bins (per sector)
+    float u0, inv_bw;    // bin = floor((u - u0) * inv_bw), clamped to [0, nbu)
+    const uint8_t *hsec; // Dv1: Y sector of every hit (null for Dv0)
 };
 
 struct GhostArgs {
@@ -142,7 +147,7 @@ struct TrackKernArgs {
 // uses them instead of keeping all of them live, and spilled to vector lanes,
 // across its whole loop.
 template <typename T>
-__device__ inline const T &kernel_args()
+__device__ __forceinline__ const T &kernel_args()
 {
     typedef const __attribute__((address_space(4))) T *cptr;
     cptr p = (cptr)__builtin_amdgcn_kernarg_segment_ptr();
@@ -152,7 +157,7 @@ __device__ inline const T &kernel_args()
 
 // Workgroup barrier ordering LDS traffic only: unlike __syncthreads it does not
 // wait for the wave's outstanding global stores.
-__device__ inline void lds_barrier()
+__device__ __forceinline__ void lds_barrier()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
@@ -160,7 +165,7 @@ __device__ inline void lds_barrier()
 }
 
 template <int BLOCK>
-__device__ inline int block_exclusive_scan(int v, int *s_wsum, int *total)
+__device__ __forceinline__ int block_exclusive_scan(int v, int *s_wsum, int *total)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     int x = v;
@@ -183,27 +188,27 @@ __device__ inline int block_exclusive_scan(int v, int *s_wsum, int *total)
     return off + x - v;
 }
 
-__device__ inline int bin_of(float u, float u0, float inv_bw, int nb)
+__device__ __forceinline__ int bin_of(float u, float u0, float inv_bw, int nb)
 {
     float t = (u - u0) * inv_bw;
     t = fminf(fmaxf(t, 0.0f), (float)(nb - 1));
     return (int)t;
 }
 
-__device__ inline bool finite5(float a, float b, float c, float d, float e)
+__device__ __forceinline__ bool finite5(float a, float b, float c, float d, float e)
 {
     return isfinite(a) && isfinite(b) && isfinite(c) && isfinite(d) && isfinite(e);
 }
 
 // Window order of hits: (|u - m|, u, index within the layer run), lexicographic.
-__device__ inline bool key_less(double da, float ua, int ia, double db, float ub, int ib)
+__device__ __forceinline__ bool key_less(double da, float ua, int ia, double db, float ub, int ib)
 {
     return da < db || (da == db && (ua < ub || (ua == ub && ia < ib)));
 }
 
 // Window order of the hit at LDS position p (distance d, coordinate u) against
 // the kept hit at position pk (distance dk; pk < 0: empty slot).
-__device__ inline bool before(const float *hu_s, const uint16_t *hidx_s, double d, float u, int p, double dk, int pk)
+__device__ __forceinline__ bool before(const float *hu_s, const uint16_t *hidx_s, double d, float u, int p, double dk, int pk)
 {
     if (d != dk || pk < 0) return d < dk || pk < 0;
     const float uk = hu_s[pk];
@@ -213,7 +218,7 @@ __device__ inline bool before(const float *hu_s, const uint16_t *hidx_s, double 
 
 // LDS positions [p_lo, p_hi) of the buckets of `layer` covering [m - W, m + W]
 // (a superset of the window: membership is decided on |u - m| <= W).
-__device__ inline void bin_range(const int *E, int layer, int nb, float u0, float inv_bw, double m, double W,
+__device__ __forceinline__ void bin_range(const int *E, int layer, int nb, float u0, float inv_bw, double m, double W,
                                  int &p_lo, int &p_hi)
 {
     const int b_lo = bin_of((float)(m - W - 1e-3), u0, inv_bw, nb);
@@ -225,7 +230,7 @@ __device__ inline void bin_range(const int *E, int layer, int nb, float u0, floa
 // Candidate key for the per-seed reduction: more hits first, then lower chi2
 // (non-negative double bits are monotone; the 8 lowest mantissa bits are
 // dropped), then lower candidate index.
-__device__ inline unsigned long long pack_key(int n, double chi2, int c)
+__device__ __forceinline__ unsigned long long pack_key(int n, double chi2, int c)
 {
     const unsigned long long b = (unsigned long long)__double_as_longlong(chi2);
     return ((unsigned long long)(4 - n) << 63) | ((b >> 8) << 7) | (unsigned long long)c;
@@ -244,7 +249,7 @@ struct FitConst {
     double w[4];
 };
 
-__device__ inline FitConst fit_const(const DevGeom &G, int mask)
+__device__ __forceinline__ FitConst fit_const(const DevGeom &G, int mask)
 {
     const int k = (mask == 15) ? 3 : (mask == 14) ? 2 : (mask == 13) ? 1 : 0;
     FitConst f;
@@ -266,7 +271,7 @@ __device__ inline FitConst fit_const(const DevGeom &G, int mask)
 // Straight-line least squares rho_L ~ alpha + beta dz_L over the layer set of
 // f; rho_L must be 0 for a layer outside the set (it then adds nothing to the
 // sums, and its weight 0 keeps it out of chi2).
-__device__ inline void fit_set(const DevGeom &G, const FitConst &f, const double rho[4], double &alpha,
+__device__ __forceinline__ void fit_set(const DevGeom &G, const FitConst &f, const double rho[4], double &alpha,
                                double &beta, double &chi2)
 {
     double sr = 0.0, szr = 0.0;
@@ -289,7 +294,7 @@ __device__ inline void fit_set(const DevGeom &G, const FitConst &f, const double
 // ------------------------------------------------------------ ghost-killer
 
 // Features of a stored track (float32 values), its seed and its hits.
-__device__ inline void ghost_features(const DevGeom &G, float xf, float yf, float txf, float tyf, float qf,
+__device__ __forceinline__ void ghost_features(const DevGeom &G, float xf, float yf, float txf, float tyf, float qf,
                                       float c2f, int nh, float sxf, float syf, float stxf, float styf, float sqf,
                                       const float hu4[4], int hasmask, float f[NF])
 {
@@ -326,7 +331,7 @@ __device__ inline void ghost_features(const DevGeom &G, float xf, float yf, floa
 typedef const __attribute__((address_space(4))) float cfloat;
 
 // 17 -> 32 ReLU -> 16 ReLU -> 1 sigmoid, float32 FMA; W is wave-uniform.
-__device__ inline float mlp_score(const float *Wg, const float f[NF])
+__device__ __forceinline__ float mlp_score(const float *Wg, const float f[NF])
 {
     // opaque to the optimiser: keeps the scalar weight loads next to their
     // uses instead of hoisting 1121 values out of the event loop into spills
@@ -357,7 +362,7 @@ __device__ inline float mlp_score(const float *Wg, const float f[NF])
 
 // ------------------------------------------------------------------ track
 
-__device__ inline void write_empty_track(const TrackArgs &a, int i)
+__device__ __forceinline__ void write_empty_track(const TrackArgs &a, int i)
 {
     if (!a.x) return;  // candidate-scoring mode writes no track slots
     a.x[i] = 0.0f;
@@ -377,13 +382,13 @@ __device__ inline void write_empty_track(const TrackArgs &a, int i)
 
 // First-window centre in UTbX: the kinked prediction of the seed.  One
 // expression for every use, so that membership tests agree bit for bit.
-__device__ inline double window1_centre(const DevGeom &G, double c3, double q)
+__device__ __forceinline__ double window1_centre(const DevGeom &G, double c3, double q)
 {
     return fma(G.mk * q, G.zm - G.zl[3], c3);
 }
 
 // Seed constants of the residual frame and the first-window centre / width.
-__device__ inline bool seed_frame(const DevGeom &G, float fsx, float fsy, float fstx, float fsty, float fsq,
+__device__ __forceinline__ bool seed_frame(const DevGeom &G, float fsx, float fsy, float fstx, float fsty, float fsq,
                                   SeedConst &sc, double &m3, double &W1)
 {
     if (!finite5(fsx, fsy, fstx, fsty, fsq)) return false;
@@ -401,25 +406,120 @@ __device__ inline bool seed_frame(const DevGeom &G, float fsx, float fsy, float 
     return true;
 }
 
+// ------------------------------------------------------------------ Dv1
+
+// Y sectors compatible with height y: those whose band
+// [y0 + k h, y0 + (k + 1) h) overlaps [y - tol, y + tol]; klo > khi (15, 0)
+// when none does.  The same division and floor as the definition.
+__device__ __forceinline__ void sector_range(const DevGeom &G, double y, int &klo, int &khi)
+{
+    const double a = (y - G.sec_tol - G.sec_y0) / G.sec_h;
+    const double b = (y + G.sec_tol - G.sec_y0) / G.sec_h;
+    const double fa = floor(a), fb = floor(b), top = (double)(G.nsec - 1);
+    if (fb < 0.0 || fa > top) {
+        klo = 15;
+        khi = 0;
+        return;
+    }
+    klo = fa < 0.0 ? 0 : (int)fa;
+    khi = fb > top ? G.nsec - 1 : (int)fb;
+}
+
+// Dv1 keeps the four layers' sector ranges in the seed constants, 4 + 4 bits
+// per layer (lo: layers 0 and 1, hi: layers 2 and 3).
+__device__ __forceinline__ void seed_sectors(const DevGeom &G, float fsy, float fsty, SeedConst &sc)
+{
+    uint32_t packed = 0;
+#pragma unroll
+    for (int L = 0; L < 4; ++L) {
+        const double yl = fma((double)fsty, G.zl[L] - G.zs, (double)fsy);
+        int klo, khi;
+        sector_range(G, yl, klo, khi);
+        packed |= (uint32_t)(klo | (khi << 4)) << (8 * L);
+    }
+    sc.lo = (uint16_t)(packed & 0xffffu);
+    sc.hi = (uint16_t)(packed >> 16);
+}
+
+__device__ __forceinline__ void sector_span(const SeedConst &sc, int L, int &klo, int &khi)
+{
+    const uint32_t v = (((uint32_t)sc.lo | ((uint32_t)sc.hi << 16)) >> (8 * L)) & 0xffu;
+    klo = (int)(v & 15u);
+    khi = (int)(v >> 4);
+}
+
+// LDS ranges of the buckets of layer L, sectors klo..khi (at most two), whose
+// u bins cover [m - W, m + W]; buckets are (layer, sector, u bin).
+__device__ __forceinline__ void sector_bins(const int *E, const TrackArgs &a, int L, int klo, int khi, double m, double W,
+                                   int &lo0, int &len0, int &lo1, int &len1)
+{
+    const int b_lo = bin_of((float)(m - W - 1e-3), a.u0, a.inv_bw, a.nbu);
+    const int b_hi = bin_of((float)(m + W + 1e-3), a.u0, a.inv_bw, a.nbu);
+    lo0 = len0 = lo1 = len1 = 0;
+    if (klo <= khi) {
+        const int base = L * a.nb + klo * a.nbu;
+        lo0 = E[base + b_lo];
+        len0 = E[base + b_hi + 1] - lo0;
+    }
+    if (klo + 1 <= khi) {
+        const int base = L * a.nb + (klo + 1) * a.nbu;
+        lo1 = E[base + b_lo];
+        len1 = E[base + b_hi + 1] - lo1;
+    }
+}
+
+// Does the line through the magnet point and the UTbX hit at p3 meet a UTaX
+// hit of a compatible sector within W (the axial triplet)?
+__device__ __forceinline__ bool dv1_triplet(const DevGeom &G, const TrackArgs &a, const float *hu_s, const int *E,
+                                   const SeedConst &sc, int k0lo, int k0hi, double W, int p3)
+{
+    const double m0 = fma((double)hu_s[p3] - sc.c[3], G.ffac[0], sc.c[0]);
+    int lo0, len0, lo1, len1;
+    sector_bins(E, a, 0, k0lo, k0hi, m0, W, lo0, len0, lo1, len1);
+    bool hit = false;
+    for (int k = 0; k < len0 + len1 && !hit; ++k) {
+        const int p = k < len0 ? lo0 + k : lo1 + (k - len0);
+        hit = fabs((double)hu_s[p] - m0) <= W;
+    }
+    return hit;
+}
+
+// Candidate key of Dv1: the candidate index holds the UTbX hit's index in its
+// layer run, 20 bits; 43 bits of chi2 above it.
+__device__ __forceinline__ unsigned long long pack_key_dv1(int n, double chi2, int c)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(chi2);
+    return ((unsigned long long)(4 - n) << 63) | ((b >> 20) << 20) | (unsigned long long)c;
+}
+
 // Every valid candidate through one UTbX hit (rank r3, LDS position p3), in
 // candidate-index order: refined windows in UTaX, UTaU, UTbV, the <= 4 option
 // tuples, their fits.  visit(n, c, alpha, beta, chi2, bp) is called for each.
-template <int N0, int N1, int N2, typename Visit>
-__device__ inline void item_candidates_n(const DevGeom &G, const TrackArgs &a, const float *hu_s,
-                                       const uint16_t *hidx_s, const int *E, const SeedConst &sc, int r3, int p3,
+template <int N0, int N1, int N2, bool DV1, typename Visit>
+__device__ __forceinline__ void item_candidates_n(const DevGeom &G, const TrackArgs &a, const float *hu_s,
+                                       const uint16_t *hidx_s, const int *E, const SeedConst &sc, int cb, int p3,
                                        Visit &&visit)
 {
     const double W2 = fma(G.w2c1, fabs((double)sc.q), G.w2c0);
     const double rho3 = (double)hu_s[p3] - sc.c[3];
     double m[3];
-    int lo[3], len[3];
+    // per layer, up to two LDS ranges (Dv1: one per compatible Y sector)
+    int lo[3], len[3], lo1[3] = {0, 0, 0}, len0[3];
     int maxlen = 0;
 #pragma unroll
     for (int L = 0; L < 3; ++L) {
         m[L] = fma(rho3, G.ffac[L], sc.c[L]);
-        int hi;
-        bin_range(E, L, a.nb, a.u0, a.inv_bw, m[L], W2, lo[L], hi);
-        len[L] = hi - lo[L];
+        if (DV1) {
+            int klo, khi, l1;
+            sector_span(sc, L, klo, khi);
+            sector_bins(E, a, L, klo, khi, m[L], W2, lo[L], len0[L], lo1[L], l1);
+            len[L] = len0[L] + l1;
+        } else {
+            int hi;
+            bin_range(E, L, a.nb, a.u0, a.inv_bw, m[L], W2, lo[L], hi);
+            len[L] = hi - lo[L];
+            len0[L] = len[L];
+        }
         maxlen = max(maxlen, len[L]);
     }
     // the three layers advance together: one LDS round trip per step; the two
@@ -430,7 +530,7 @@ __device__ inline void item_candidates_n(const DevGeom &G, const TrackArgs &a, c
 #pragma unroll
         for (int L = 0; L < 3; ++L) {
             if (k >= len[L]) continue;
-            const int p = lo[L] + k;
+            const int p = (!DV1 || k < len0[L]) ? lo[L] + k : lo1[L] + (k - len0[L]);
             const float u = hu_s[p];
             const double d = fabs((double)u - m[L]);
             if (!(d <= W2)) continue;
@@ -461,6 +561,7 @@ __device__ inline void item_candidates_n(const DevGeom &G, const TrackArgs &a, c
     const int mask = 8 | (nA[0] > 0 ? 1 : 0) | (nA[1] > 0 ? 2 : 0) | (nA[2] > 0 ? 4 : 0);
     const int n = __popc(mask);
     if (n < 3 || (mask & 3) == 0) return;
+    if (DV1 && nA[0] == 0) return;   // the axial triplet needs its UTaX hit
     const FitConst fc = fit_const(G, mask);
     double r0[N0], r1[N1], r2[N2];
 #pragma unroll
@@ -483,7 +584,7 @@ __device__ inline void item_candidates_n(const DevGeom &G, const TrackArgs &a, c
                 double al, be, c2;
                 fit_set(G, fc, rho, al, be, c2);
                 const int bp[4] = {A[0][i0], A[1][i1], A[2][i2], p3};
-                visit(n, ((r3 * G.nw[0] + i0) * G.nw[1] + i1) * G.nw[2] + i2, al, be, c2, bp);
+                visit(n, ((cb * G.nw[0] + i0) * G.nw[1] + i1) * G.nw[2] + i2, al, be, c2, bp);
             }
         }
     }
@@ -491,20 +592,21 @@ __device__ inline void item_candidates_n(const DevGeom &G, const TrackArgs &a, c
 
 // The paper's (1, 2, 2) closest hits are compiled on their own; other settings
 // take the generic (<= 2, <= 2, <= 2) enumeration.  Same visiting order.
-template <typename Visit>
-__device__ inline void item_candidates(const DevGeom &G, const TrackArgs &a, const float *hu_s,
-                                       const uint16_t *hidx_s, const int *E, const SeedConst &sc, int r3, int p3,
+// cb: the UTbX hit's rank in its window (Dv0) or its index in its layer run (Dv1).
+template <bool DV1 = false, typename Visit>
+__device__ __forceinline__ void item_candidates(const DevGeom &G, const TrackArgs &a, const float *hu_s,
+                                       const uint16_t *hidx_s, const int *E, const SeedConst &sc, int cb, int p3,
                                        Visit &&visit)
 {
     if (G.ncl[0] == 1 && G.ncl[1] == 2 && G.ncl[2] == 2)
-        item_candidates_n<1, 2, 2>(G, a, hu_s, hidx_s, E, sc, r3, p3, visit);
+        item_candidates_n<1, 2, 2, DV1>(G, a, hu_s, hidx_s, E, sc, cb, p3, visit);
     else
-        item_candidates_n<MAX_CLOSEST, MAX_CLOSEST, MAX_CLOSEST>(G, a, hu_s, hidx_s, E, sc, r3, p3, visit);
+        item_candidates_n<MAX_CLOSEST, MAX_CLOSEST, MAX_CLOSEST, DV1>(G, a, hu_s, hidx_s, E, sc, cb, p3, visit);
 }
 
 // Rank of the UTbX hit at p3 among the seed's first-window hits (by the
 // window key), or -1 if it is outside the window.
-__device__ inline int first_window_rank(const DevGeom &G, const float *hu_s, const uint16_t *hidx_s,
+__device__ __forceinline__ int first_window_rank(const DevGeom &G, const float *hu_s, const uint16_t *hidx_s,
                                         const SeedConst &sc, int p3)
 {
     const double W1 = fma(G.w1c1, fabs((double)sc.q), G.w1c0);
@@ -523,14 +625,15 @@ __device__ inline int first_window_rank(const DevGeom &G, const float *hu_s, con
 }
 
 // Best candidate through one UTbX hit: more hits, then lower chi2, then lower index.
-__device__ inline void item_best(const DevGeom &G, const TrackArgs &a, const float *hu_s, const uint16_t *hidx_s,
-                                 const int *E, const SeedConst &sc, int r3, int p3, int &best_n, double &best_chi2,
+template <bool DV1 = false>
+__device__ __forceinline__ void item_best(const DevGeom &G, const TrackArgs &a, const float *hu_s, const uint16_t *hidx_s,
+                                 const int *E, const SeedConst &sc, int cb, int p3, int &best_n, double &best_chi2,
                                  int &best_c, int bp_out[4])
 {
     best_n = 0;
     best_chi2 = 0.0;
     best_c = -1;
-    item_candidates(G, a, hu_s, hidx_s, E, sc, r3, p3,
+    item_candidates<DV1>(G, a, hu_s, hidx_s, E, sc, cb, p3,
                     [&](int n, int c, double, double, double c2, const int bp[4]) {
                         if (n > best_n || (n == best_n && c2 < best_chi2)) {
                             best_n = n;
@@ -547,7 +650,7 @@ struct StoredTrack {
     float x, y, tx, ty, qop, chi2, score;
 };
 
-__device__ inline StoredTrack stored_track(const TrackArgs &a, const DevGeom &G, int i, int n, double al, double be,
+__device__ __forceinline__ StoredTrack stored_track(const TrackArgs &a, const DevGeom &G, int i, int n, double al, double be,
                                            double c2, const float *hu_s, const int bp[4], bool score)
 {
     const float fsx = a.sx[i], fsy = a.sy[i], fstx = a.stx[i], fsty = a.sty[i], fsq = a.sqop[i];
@@ -576,7 +679,7 @@ __device__ inline StoredTrack stored_track(const TrackArgs &a, const DevGeom &G,
 }
 
 // Write the selected candidate (LDS positions bp, -1 = none) as seed i's track.
-__device__ inline StoredTrack write_track(const TrackArgs &a, const DevGeom &G, int i, const SeedConst &sc,
+__device__ __forceinline__ StoredTrack write_track(const TrackArgs &a, const DevGeom &G, int i, const SeedConst &sc,
                                           const float *hu_s, const uint16_t *hidx_s, const int bp[4], int c)
 {
     const int mask = (bp[0] >= 0 ? 1 : 0) | (bp[1] >= 0 ? 2 : 0) | (bp[2] >= 0 ? 4 : 0) | 8;
@@ -604,7 +707,7 @@ __device__ inline StoredTrack write_track(const TrackArgs &a, const DevGeom &G, 
 }
 
 // One row per (seed, candidate index) of the candidate-scoring mode.
-__device__ inline void write_candidate_row(const TrackArgs &a, const DevGeom &G, int i, int n, int c, double al,
+__device__ __forceinline__ void write_candidate_row(const TrackArgs &a, const DevGeom &G, int i, int n, int c, double al,
                                            double be, double c2, const float *hu_s, const uint16_t *hidx_s,
                                            const int bp[4])
 {
@@ -630,8 +733,21 @@ __device__ inline void write_candidate_row(const TrackArgs &a, const DevGeom &G,
 // start of bucket b and E[4*nb] = count.  Hits are read HPT per lane per round
 // with all loads in flight; events of one round keep them in registers
 // between the counting and the placing pass.
-template <int BLOCK, typename Between>
-__device__ inline bool stage_hits(const TrackArgs &a, int hb, const int hl[4], int nh, float *hu_s,
+// Bucket of a hit: (layer, u bin) for Dv0; (layer, Y sector, u bin) for Dv1,
+// with one last bucket per layer for sector ids outside [0, nsec).
+template <bool DV1>
+__device__ __forceinline__ int hit_bucket(const TrackArgs &a, int nsec, int L, float u, int k)
+{
+    int b = L * a.nb + bin_of(u, a.u0, a.inv_bw, a.nbu);
+    if (DV1) {
+        const int sec = a.hsec[k];
+        b = sec < nsec ? b + sec * a.nbu : L * a.nb + nsec * a.nbu;
+    }
+    return b;
+}
+
+template <int BLOCK, bool DV1, typename Between>
+__device__ __forceinline__ bool stage_hits(const TrackArgs &a, int nsec, int hb, const int hl[4], int nh, float *hu_s,
                                   uint16_t *hidx_s, int *E, int *s_bad, int *s_wsum, Between &&between)
 {
     constexpr int HPT = 16;
@@ -668,7 +784,7 @@ __device__ inline bool stage_hits(const TrackArgs &a, int hb, const int hl[4], i
                     bad = true;
                 } else {
                     const int L = (k >= hl[1]) + (k >= hl[2]) + (k >= hl[3]);
-                    atomicAdd(&E[L * a.nb + bin_of(u[j], a.u0, a.inv_bw, a.nb) + 1], 1);
+                    atomicAdd(&E[hit_bucket<DV1>(a, nsec, L, u[j], hb + k) + 1], 1);
                 }
             }
         }
@@ -677,12 +793,13 @@ __device__ inline bool stage_hits(const TrackArgs &a, int hb, const int hl[4], i
     lds_barrier();
     if (*s_bad) return false;
     // exclusive scan of the bucket counts held at E[1..NBT]: E[b + 1] = start of bucket b
-    const int per = NBT / BLOCK;
+    const int per = (NBT + BLOCK - 1) / BLOCK;
+    const int j_end = min(per, NBT - tid * per);   // may be <= 0 for the last lanes
     int local = 0;
-    for (int j = 0; j < per; ++j) local += E[1 + tid * per + j];
+    for (int j = 0; j < j_end; ++j) local += E[1 + tid * per + j];
     int tot;
     int run = block_exclusive_scan<BLOCK>(local, s_wsum, &tot);
-    for (int j = 0; j < per; ++j) {
+    for (int j = 0; j < j_end; ++j) {
         const int cnt = E[1 + tid * per + j];
         E[1 + tid * per + j] = run;
         run += cnt;
@@ -703,7 +820,7 @@ __device__ inline bool stage_hits(const TrackArgs &a, int hb, const int hl[4], i
             const int k = k0 + j * BLOCK;
             if (k < nh) {
                 const int L = (k >= hl[1]) + (k >= hl[2]) + (k >= hl[3]);
-                const int pos = atomicAdd(&E[L * a.nb + bin_of(u[j], a.u0, a.inv_bw, a.nb) + 1], 1);
+                const int pos = atomicAdd(&E[hit_bucket<DV1>(a, nsec, L, u[j], hb + k) + 1], 1);
                 hu_s[pos] = u[j];
                 hidx_s[pos] = (uint16_t)(k - hl[L]);
             }
@@ -713,18 +830,18 @@ __device__ inline bool stage_hits(const TrackArgs &a, int hb, const int hl[4], i
     return true;
 }
 
-__device__ inline void unrank_pair(int k, int n, int &pa, int &pb);
-__device__ inline bool pca64(const DevGeom &G, double x1, double y1, double tx1, double ty1, double g1, double x2,
+__device__ __forceinline__ void unrank_pair(int k, int n, int &pa, int &pb);
+__device__ __forceinline__ bool pca64(const DevGeom &G, double x1, double y1, double tx1, double ty1, double g1, double x2,
                              double y2, double tx2, double ty2, double g2, double &vx, double &vy, double &vz,
                              double &doca, double &s_out, double &t_out);
-__device__ inline void vertex_extras(const DevGeom &G, const float *WLg, float4 A, float4 B, double g1, double g2,
+__device__ __forceinline__ void vertex_extras(const DevGeom &G, const float *WLg, float4 A, float4 B, double g1, double g2,
                                      float q1, float q2, double s, double t, float4 V, float out[6]);
 
 // Vertexing of one event by the whole workgroup, from the kept tracks in LDS
 // (slot order): pairs (a < b) in row-major chunks of BLOCK, float32
 // prescreen, float64 Newton PCA of the survivors, order-preserving output.
 template <int BLOCK>
-__device__ inline void vertex_event_block(const TrackArgs &a, const DevGeom &G, int e, int s0, int n,
+__device__ __forceinline__ void vertex_event_block(const TrackArgs &a, const DevGeom &G, int e, int s0, int n,
                                           const float4 *kst, const float *kq, const int *kslot, int *qk, int *qpass,
                                           float4 *qres, float2 *qst, int *s_wsum)
 {
@@ -808,7 +925,7 @@ __device__ inline void vertex_event_block(const TrackArgs &a, const DevGeom &G, 
 
 // Event of launch iteration `iter`: the work counter of a persistent launch,
 // or the one event of a per-event launch.
-__device__ inline int grab_event(const TrackArgs &a, int iter)
+__device__ __forceinline__ int grab_event(const TrackArgs &a, int iter)
 {
     if (a.ev_single >= 0) return iter == 0 ? a.ev_single : a.n_events;
     return atomicAdd(&a.counter[0], 1);
@@ -816,7 +933,7 @@ __device__ inline int grab_event(const TrackArgs &a, int iter)
 
 // One whole wave: the event of iteration `iter` and its offsets into LDS,
 // s_nx = {event, seed_off[e], seed_off[e + 1], hit_off[4e .. 4e + 4]}.
-__device__ inline void fetch_event(const TrackArgs &a, int iter, int lane, int *s_nx)
+__device__ __forceinline__ void fetch_event(const TrackArgs &a, int iter, int lane, int *s_nx)
 {
     int en = 0;
     if (lane == 0) en = grab_event(a, iter);
@@ -825,9 +942,10 @@ __device__ inline void fetch_event(const TrackArgs &a, int iter, int lane, int *
     if (lane < 7 && en < a.n_events) s_nx[1 + lane] = lane < 2 ? a.seed_off[en + lane] : a.hit_off[4 * en + lane - 2];
 }
 
-template <int BLOCK, bool CANDS, bool VTX>
+template <int BLOCK, bool CANDS, bool VTX, bool DV1>
 __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
 {
+    static_assert(!(CANDS && DV1), "candidate rows follow Dv0");
     const TrackArgs &a0 = kernel_args<TrackKernArgs>().a;
     extern __shared__ __align__(16) unsigned char smem[];
     size_t off = 0;
@@ -912,11 +1030,13 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
                 if (!seed_frame(G, a.sx[i], a.sy[i], a.stx[i], a.sty[i], a.sqop[i], sc, m3, W1)) {
                     atomicOr(a.flags, F_NONFINITE);
                     sc.q = __int_as_float(0x7fc00000);   // NaN: no frame
+                } else if (DV1) {
+                    seed_sectors(G, a.sy[i], a.sty[i], sc);
                 }
                 s_c[tid] = sc;
             }
         };
-        if (!stage_hits<BLOCK>(a, ho[0], hl, nh, hu_s, hidx_s, E, &s_bad, s_wsum, first_frames)) {
+        if (!stage_hits<BLOCK, DV1>(a, G.nsec, ho[0], hl, nh, hu_s, hidx_s, E, &s_bad, s_wsum, first_frames)) {
             if (tid == 0) atomicOr(a.flags, F_NONFINITE);
             if (VTX && tid == 0) a.vcount[e] = 0;
             for (int i = s0 + tid; i < s1; i += BLOCK) write_empty_track(a, i);
@@ -951,16 +1071,36 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
                 } else {
                     ok = seed_frame(G, a.sx[i], a.sy[i], a.stx[i], a.sty[i], a.sqop[i], sc, m3, W1);
                     if (!ok) atomicOr(a.flags, F_NONFINITE);
+                    else if (DV1) seed_sectors(G, a.sy[i], a.sty[i], sc);
                 }
                 if (ok) {
-                    if (G.max_l3 > 0) bin_range(E, 3, a.nb, a.u0, a.inv_bw, m3, W1, p_lo, p_hi);
+                    if (DV1) {
+                        // Dv1: every UTbX hit of the compatible sectors, no momentum window
+                        int klo, khi;
+                        sector_span(sc, 3, klo, khi);
+                        if (klo <= khi) {
+                            p_lo = E[3 * a.nb + klo * a.nbu];
+                            p_hi = E[3 * a.nb + (khi + 1) * a.nbu];
+                        }
+                    } else if (G.max_l3 > 0) {
+                        bin_range(E, 3, a.nb, a.u0, a.inv_bw, m3, W1, p_lo, p_hi);
+                    }
                     n_rng = p_hi - p_lo;
                 }
             }
-            sc.lo = (uint16_t)p_lo;
-            sc.hi = (uint16_t)p_hi;
+            if (!DV1) {   // Dv1 keeps its sector spans in lo / hi
+                sc.lo = (uint16_t)p_lo;
+                sc.hi = (uint16_t)p_hi;
+            }
+            // an item per UTbX hit inside the first window (Dv0) or per axial triplet (Dv1)
+            const double W2 = DV1 ? fma(G.w2c1, fabs((double)sc.q), G.w2c0) : 0.0;
+            int k0lo = 0, k0hi = -1;
+            if (DV1) sector_span(sc, 0, k0lo, k0hi);
+            auto is_item = [&](int p) {
+                return DV1 ? dv1_triplet(G, a, hu_s, E, sc, k0lo, k0hi, W2, p) : fabs((double)hu_s[p] - m3) <= W1;
+            };
             int n_win = 0;
-            for (int k = 0; k < n_rng; ++k) n_win += fabs((double)hu_s[p_lo + k] - m3) <= W1 ? 1 : 0;
+            for (int k = 0; k < n_rng; ++k) n_win += is_item(p_lo + k) ? 1 : 0;
             int tot;
             const int excl = block_exclusive_scan<BLOCK>(n_win, s_wsum, &tot);
             bool acc = have && (excl + n_win <= a.icap);
@@ -977,8 +1117,7 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
                 s_base[tid] = excl;
                 atomicMax(&s_nitems, excl + n_win);
                 for (int k = 0, w = 0; k < n_rng && w < n_win; ++k) {
-                    if (fabs((double)hu_s[p_lo + k] - m3) <= W1)
-                        it_desc[excl + w++] = ((uint32_t)tid << 16) | (uint32_t)(p_lo + k);
+                    if (is_item(p_lo + k)) it_desc[excl + w++] = ((uint32_t)tid << 16) | (uint32_t)(p_lo + k);
                 }
             }
             lds_barrier();
@@ -992,8 +1131,13 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
                 const uint32_t d = it_desc[it];
                 const int sl = (int)(d >> 16), p3 = (int)(d & 0xffffu);
                 const SeedConst scs = s_c[sl];
-                const int r3 = first_window_rank(G, hu_s, hidx_s, scs, p3);
-                if (r3 < 0 || r3 >= G.max_l3) continue;
+                int r3;
+                if (DV1) {
+                    r3 = hidx_s[p3];   // Dv1 candidate index: the UTbX hit's index in its run
+                } else {
+                    r3 = first_window_rank(G, hu_s, hidx_s, scs, p3);
+                    if (r3 < 0 || r3 >= G.max_l3) continue;
+                }
                 if (CANDS) {
                     item_candidates(G, a, hu_s, hidx_s, E, scs, r3, p3,
                                     [&](int n, int c, double al, double be, double c2, const int bp[4]) {
@@ -1003,14 +1147,14 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
                 }
                 int bn, bc, bp[4] = {-1, -1, -1, -1};
                 double bchi2;
-                item_best(G, a, hu_s, hidx_s, E, scs, r3, p3, bn, bchi2, bc, bp);
+                item_best<DV1>(G, a, hu_s, hidx_s, E, scs, r3, p3, bn, bchi2, bc, bp);
                 if (bn > 0) {
                     unsigned long long packed = 0;
 #pragma unroll
                     for (int L = 0; L < 4; ++L)
                         packed |= (unsigned long long)(bp[L] >= 0 ? (unsigned)bp[L] : 0xffffu) << (16 * L);
-                    it_hits[s_base[sl] + r3] = packed;
-                    atomicMin(&s_key[sl], pack_key(bn, bchi2, bc));
+                    it_hits[DV1 ? it : s_base[sl] + r3] = packed;
+                    atomicMin(&s_key[sl], DV1 ? pack_key_dv1(bn, bchi2, bc) : pack_key(bn, bchi2, bc));
                 }
             }
             lds_barrier();
@@ -1023,8 +1167,17 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
                 if (key == ~0ull) {
                     write_empty_track(a, i);
                 } else {
-                    const int c = (int)(key & 127ull);
-                    const unsigned long long hp = it_hits[s_base[tid] + c / per_r3];
+                    const int c = (int)(key & (DV1 ? 0xfffffull : 127ull));
+                    int slot = s_base[tid] + c / per_r3;
+                    if (DV1) {
+                        // the seed's item whose UTbX hit has the winning index
+                        const int i3 = c / per_r3;
+                        const int b1 = tid + 1 < nacc ? s_base[tid + 1] : n_items;
+                        slot = s_base[tid];
+                        for (int it = s_base[tid]; it < b1; ++it)
+                            slot = (int)hidx_s[it_desc[it] & 0xffffu] == i3 ? it : slot;
+                    }
+                    const unsigned long long hp = it_hits[slot];
                     int bp[4];
 #pragma unroll
                     for (int L = 0; L < 4; ++L) {
@@ -1167,7 +1320,7 @@ __global__ __launch_bounds__(BLOCK) void k_ghost(GhostArgs a, DevGeom G)
 // Newton-Raphson point of closest approach in float64.  Offsets s, t are
 // z - z_ref on each trajectory.  Returns false for (near-)parallel tracks or
 // a singular Newton system.
-__device__ inline bool pca64(const DevGeom &G, double x1, double y1, double tx1, double ty1, double g1, double x2,
+__device__ __forceinline__ bool pca64(const DevGeom &G, double x1, double y1, double tx1, double ty1, double g1, double x2,
                              double y2, double tx2, double ty2, double g2, double &vx, double &vy, double &vz,
                              double &doca, double &s_out, double &t_out)
 {
@@ -1212,7 +1365,7 @@ __device__ inline bool pca64(const DevGeom &G, double x1, double y1, double tx1,
 }
 
 // Row-major rank k of the pair (a, b), a < b < n, back to (a, b).
-__device__ inline void unrank_pair(int k, int n, int &pa, int &pb)
+__device__ __forceinline__ void unrank_pair(int k, int n, int &pa, int &pb)
 {
     const double tn = 2.0 * n - 1.0;
     int r = (int)floor((tn - sqrt(fmax(tn * tn - 8.0 * (double)k, 0.0))) * 0.5);
@@ -1228,7 +1381,7 @@ __device__ inline void unrank_pair(int k, int n, int &pa, int &pb)
 // proton; MeV) from the seed momenta and the trajectory tangents at the points
 // of closest approach (offsets s, t from z_ref), then the four trigger-line
 // networks (12 -> 32 ReLU -> 1 sigmoid, float32) on the pair and the vertex.
-__device__ inline void vertex_extras(const DevGeom &G, const float *WLg, float4 A, float4 B, double g1, double g2,
+__device__ __forceinline__ void vertex_extras(const DevGeom &G, const float *WLg, float4 A, float4 B, double g1, double g2,
                                      float q1, float q2, double s, double t, float4 V, float out[6])
 {
     const double MPI = 0.13957039, MPR = 0.93827209;
@@ -1277,14 +1430,14 @@ __device__ inline void vertex_extras(const DevGeom &G, const float *WLg, float4 
     }
 }
 
-__device__ inline void wave_sync()
+__device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ inline int wave_exclusive_scan(int v, int *total)
+__device__ __forceinline__ int wave_exclusive_scan(int v, int *total)
 {
     const int lane = threadIdx.x & 63;
     int x = v;

@@ -43,6 +43,9 @@ class DsGeometry(C.Structure):
         ("doca_max", C.c_double),
         ("ghost_threshold", C.c_double),
         ("clone_kill", C.c_int32),
+        ("algorithm", C.c_int32),
+        ("n_sectors", C.c_int32),
+        ("sector_y0", C.c_double), ("sector_h", C.c_double), ("sector_tol", C.c_double),
     ]
 
 
@@ -54,6 +57,7 @@ class DsEvents(C.Structure):
         ("sx", C.c_void_p), ("sy", C.c_void_p), ("stx", C.c_void_p), ("sty", C.c_void_p), ("sqop", C.c_void_p),
         ("hit_off", C.c_void_p),
         ("hu", C.c_void_p),
+        ("hit_sector", C.c_void_p),
     ]
 
 
@@ -151,6 +155,11 @@ def geometry_struct(g: Dict) -> DsGeometry:
     s.n_closest[:] = [int(v) for v in g["n_closest"]]
     s.newton_iters = int(g["newton_iters"])
     s.clone_kill = int(g.get("clone_kill", 0))
+    s.algorithm = int(g.get("algorithm", 0))
+    s.n_sectors = int(g.get("n_sectors", 1))
+    s.sector_y0 = float(g.get("sector_y0", -700.0))
+    s.sector_h = float(g.get("sector_h", 1400.0))
+    s.sector_tol = float(g.get("sector_tol", 0.0))
     return s
 
 
@@ -180,6 +189,8 @@ class DeviceEvents:
                                                            f(batch.sqop))
         self.hit_off = f(batch.hit_off.astype(np.int32))
         self.hu = f(batch.hu)
+        sec = getattr(batch, "hit_sector", None)
+        self.hit_sector = f(sec.astype(np.uint8)) if sec is not None and len(sec) else None
         ms = int(np.max(np.diff(batch.seed_off))) if batch.n_events else 0
         mh = int(np.max(batch.hit_off[4::4] - batch.hit_off[0:-1:4])) if batch.n_events else 0
         self.n_events, self.n_seeds, self.n_hits = batch.n_events, batch.n_seeds, batch.n_hits
@@ -195,6 +206,7 @@ class DeviceEvents:
         s.sx, s.sy, s.stx, s.sty, s.sqop = (_ptr(self.sx), _ptr(self.sy), _ptr(self.stx), _ptr(self.sty),
                                             _ptr(self.sqop))
         s.hu = _ptr(self.hu)
+        s.hit_sector = _ptr(self.hit_sector)
         return s
 
 

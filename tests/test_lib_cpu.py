@@ -48,6 +48,8 @@ int main(void) {
          sizeof(ds_events), sizeof(ds_tracks), sizeof(ds_vertices));
   P(ds_geometry, max_l3) P(ds_geometry, n_closest) P(ds_geometry, gamma_c0) P(ds_geometry, newton_iters)
   P(ds_geometry, doca_max) P(ds_geometry, ghost_threshold) P(ds_geometry, clone_kill) P(ds_events, seed_off) P(ds_events, hu)
+  P(ds_geometry, algorithm) P(ds_geometry, n_sectors) P(ds_geometry, sector_y0) P(ds_geometry, sector_tol)
+  P(ds_events, hit_sector)
   P(ds_tracks, hit) P(ds_tracks, nhits) P(ds_tracks, flags) P(ds_vertices, count) P(ds_vertices, flags) P(ds_vertices, m_pipi) P(ds_vertices, line)
   return 0;
 }
