@@ -778,6 +778,7 @@ __device__ __forceinline__ bool stage_hits(const TrackArgs &a, int nsec, int hb,
         bool bad = false;
 #pragma unroll
         for (int j = 0; j < HPT; ++j) {
+            if ((r * HPT + j) * BLOCK >= nh) break;   // uniform: no lane has slot j
             const int k = k0 + j * BLOCK;
             if (k < nh) {
                 if (!isfinite(u[j])) {
@@ -817,6 +818,7 @@ __device__ __forceinline__ bool stage_hits(const TrackArgs &a, int nsec, int hb,
         }
 #pragma unroll
         for (int j = 0; j < HPT; ++j) {
+            if ((r * HPT + j) * BLOCK >= nh) break;   // uniform: no lane has slot j
             const int k = k0 + j * BLOCK;
             if (k < nh) {
                 const int L = (k >= hl[1]) + (k >= hl[2]) + (k >= hl[3]);
@@ -1052,7 +1054,7 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
             const DevGeom &G = Kc.G;
             if (tid == 0) {
                 s_nacc = min(BLOCK, s1 - sc0);
-                s_nitems = 0;
+                s_nitems = INT_MAX;
             }
             // phase A: lane per seed, the UTbX bucket range of its first window;
             // every hit of the range inside the window becomes an item (seed, hit)
@@ -1110,18 +1112,23 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
                 n_win = a.icap;
                 acc = true;
             }
-            if (have && !acc) atomicMin(&s_nacc, tid);
+            // acceptance is a prefix of the chunk; only the (rare) refused seeds
+            // touch the shared counters: the first refused one ends the chunk
+            // and its exclusive offset is the chunk's item count
+            if (have && !acc) {
+                atomicMin(&s_nacc, tid);
+                atomicMin(&s_nitems, excl);
+            }
             if (acc) {
                 s_c[tid] = sc;
                 s_key[tid] = ~0ull;
                 s_base[tid] = excl;
-                atomicMax(&s_nitems, excl + n_win);
                 for (int k = 0, w = 0; k < n_rng && w < n_win; ++k) {
                     if (is_item(p_lo + k)) it_desc[excl + w++] = ((uint32_t)tid << 16) | (uint32_t)(p_lo + k);
                 }
             }
             lds_barrier();
-            const int nacc = s_nacc, n_items = s_nitems;
+            const int nacc = s_nacc, n_items = min(min(tot, s_nitems), a.icap);
             if (sc0 == s0 && tid >= BLOCK - 64) fetch_event(a, iter + 1, tid - (BLOCK - 64), s_nx);
             // phase B: lane per (seed, UTbX hit) item
             for (int it = tid; it < n_items; it += BLOCK) {
