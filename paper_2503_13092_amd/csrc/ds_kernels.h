@@ -164,16 +164,25 @@ __device__ __forceinline__ void lds_barrier()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Inclusive sum over the 64 lanes of a wavefront, in lane order: four doubling
+// row shifts within rows of 16 lanes, then the row broadcasts of lanes 15 and
+// 31 (DPP, no LDS traffic).  Lanes outside a shift's source read 0.
+__device__ __forceinline__ int wave_inclusive_sum(int x)
+{
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);   // row_bcast:15 into rows 1, 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);   // row_bcast:31 into rows 2, 3
+    return x;
+}
+
 template <int BLOCK>
 __device__ __forceinline__ int block_exclusive_scan(int v, int *s_wsum, int *total)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
+    const int x = wave_inclusive_sum(v);
     if (lane == 63) s_wsum[wid] = x;
     lds_barrier();
     int off = 0, tot = 0;
@@ -1446,14 +1455,8 @@ __device__ __forceinline__ void wave_sync()
 
 __device__ __forceinline__ int wave_exclusive_scan(int v, int *total)
 {
-    const int lane = threadIdx.x & 63;
-    int x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
-    *total = __shfl(x, 63, 64);
+    const int x = wave_inclusive_sum(v);
+    *total = __builtin_amdgcn_readlane(x, 63);
     return x - v;
 }
 
