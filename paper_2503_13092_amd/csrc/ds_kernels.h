@@ -536,11 +536,20 @@ __device__ __forceinline__ void item_candidates_n(const DevGeom &G, const TrackA
     double d0[3] = {INFINITY, INFINITY, INFINITY}, d1[3] = {INFINITY, INFINITY, INFINITY};
     int p0k[3] = {-1, -1, -1}, p1k[3] = {-1, -1, -1};
     for (int k = 0; k < maxlen; ++k) {
+        // the three loads first (a finished layer re-reads its start), then the tests
+        int pp[3];
+        float uu[3];
+#pragma unroll
+        for (int L = 0; L < 3; ++L) {
+            const int kk = k < len[L] ? k : 0;
+            pp[L] = (!DV1 || kk < len0[L]) ? lo[L] + kk : lo1[L] + (kk - len0[L]);
+            uu[L] = hu_s[pp[L]];
+        }
 #pragma unroll
         for (int L = 0; L < 3; ++L) {
             if (k >= len[L]) continue;
-            const int p = (!DV1 || k < len0[L]) ? lo[L] + k : lo1[L] + (k - len0[L]);
-            const float u = hu_s[p];
+            const int p = pp[L];
+            const float u = uu[L];
             const double d = fabs((double)u - m[L]);
             if (!(d <= W2)) continue;
             const int NL = L == 0 ? N0 : (L == 1 ? N1 : N2);
