@@ -485,8 +485,12 @@ __device__ __forceinline__ bool dv1_triplet(const DevGeom &G, const TrackArgs &a
     const double m0 = fma((double)hu_s[p3] - sc.c[3], G.ffac[0], sc.c[0]);
     int lo0, len0, lo1, len1;
     sector_bins(E, a, 0, k0lo, k0hi, m0, W, lo0, len0, lo1, len1);
-    bool hit = false;
-    for (int k = 0; k < len0 + len1 && !hit; ++k) {
+    // the first two positions are read together (most probes look at <= 2 hits)
+    const int n = len0 + len1;
+    const int pa = len0 > 0 ? lo0 : lo1, pb = len0 > 1 ? lo0 + 1 : (len0 == 1 ? lo1 : lo1 + 1);
+    const float ua = hu_s[n > 0 ? pa : 0], ub = hu_s[n > 1 ? pb : 0];
+    bool hit = (n > 0 && fabs((double)ua - m0) <= W) || (n > 1 && fabs((double)ub - m0) <= W);
+    for (int k = 2; k < n && !hit; ++k) {
         const int p = k < len0 ? lo0 + k : lo1 + (k - len0);
         hit = fabs((double)hu_s[p] - m0) <= W;
     }
@@ -1120,7 +1124,38 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
                 return DV1 ? dv1_triplet(G, a, hu_s, E, sc, k0lo, k0hi, W2, p) : fabs((double)hu_s[p] - m3) <= W1;
             };
             int n_win = 0;
-            for (int k = 0; k < n_rng; ++k) n_win += is_item(p_lo + k) ? 1 : 0;
+            // Dv1 tests its axial triplets a wavefront per seed, a lane per UTbX
+            // hit (tens of hits per seed): the seed constants and ranges go to LDS
+            int *s_pk = reinterpret_cast<int *>(it_hits);   // free until phase B
+            int *s_cnt = reinterpret_cast<int *>(s_key);    // free until the scan below
+            // triplet flags of a seed's first 128 UTbX hits, kept for the write pass
+            unsigned long long *s_mask = it_hits + BLOCK / 2;
+            const int lane = tid & 63, wave = tid >> 6;
+            const int n_chunk = min(BLOCK, s1 - sc0);
+            if (DV1) {
+                s_c[tid] = sc;
+                s_pk[tid] = p_lo | (n_rng << 16);
+                lds_barrier();
+                for (int sl = wave; sl < n_chunk; sl += BLOCK / 64) {
+                    const int pk = s_pk[sl], plo = pk & 0xffff, nr = pk >> 16;
+                    const SeedConst scw = s_c[sl];
+                    const double W2w = fma(G.w2c1, fabs((double)scw.q), G.w2c0);
+                    int klo, khi;
+                    sector_span(scw, 0, klo, khi);
+                    int cnt = 0;
+                    for (int k0 = 0; k0 < nr; k0 += 64) {
+                        const bool f = k0 + lane < nr && dv1_triplet(G, a, hu_s, E, scw, klo, khi, W2w, plo + k0 + lane);
+                        const unsigned long long m = __ballot(f);
+                        if (k0 < 128 && lane == 0) s_mask[2 * sl + (k0 >> 6)] = m;
+                        cnt += __popcll(m);
+                    }
+                    if (lane == 0) s_cnt[sl] = cnt;
+                }
+                lds_barrier();
+                n_win = have ? s_cnt[tid] : 0;
+            } else {
+                for (int k = 0; k < n_rng; ++k) n_win += is_item(p_lo + k) ? 1 : 0;
+            }
             int tot;
             const int excl = block_exclusive_scan<BLOCK>(n_win, s_wsum, &tot);
             bool acc = have && (excl + n_win <= a.icap);
@@ -1141,8 +1176,37 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
                 s_c[tid] = sc;
                 s_key[tid] = ~0ull;
                 s_base[tid] = excl;
-                for (int k = 0, w = 0; k < n_rng && w < n_win; ++k) {
-                    if (is_item(p_lo + k)) it_desc[excl + w++] = ((uint32_t)tid << 16) | (uint32_t)(p_lo + k);
+                if (!DV1) {
+                    for (int k = 0, w = 0; k < n_rng && w < n_win; ++k) {
+                        if (is_item(p_lo + k)) it_desc[excl + w++] = ((uint32_t)tid << 16) | (uint32_t)(p_lo + k);
+                    }
+                }
+            }
+            if (DV1) {
+                // the triplets again, written in hit order at the seed's base
+                lds_barrier();
+                const int nacc_w = s_nacc, nit_w = min(min(tot, s_nitems), a.icap);
+                for (int sl = wave; sl < nacc_w; sl += BLOCK / 64) {
+                    const int pk = s_pk[sl], plo = pk & 0xffff, nr = pk >> 16;
+                    const SeedConst scw = s_c[sl];
+                    const double W2w = fma(G.w2c1, fabs((double)scw.q), G.w2c0);
+                    int klo, khi;
+                    sector_span(scw, 0, klo, khi);
+                    const int base = s_base[sl], cap = (sl + 1 < nacc_w ? s_base[sl + 1] : nit_w) - base;
+                    int w = 0;
+                    for (int k0 = 0; k0 < nr && w < cap; k0 += 64) {
+                        bool f;
+                        if (k0 < 128)
+                            f = (s_mask[2 * sl + (k0 >> 6)] >> lane) & 1ull;
+                        else
+                            f = k0 + lane < nr && dv1_triplet(G, a, hu_s, E, scw, klo, khi, W2w, plo + k0 + lane);
+                        const unsigned long long m = __ballot(f);
+                        const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                                   __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+                        if (f && w + pre < cap)
+                            it_desc[base + w + pre] = ((uint32_t)sl << 16) | (uint32_t)(plo + k0 + lane);
+                        w += __popcll(m);
+                    }
                 }
             }
             lds_barrier();
