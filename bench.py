@@ -88,7 +88,14 @@ def cpu_baseline(batch, g, w):
     t0 = time.perf_counter()
     O.run_path(sample, g, w, cap=64, n_threads=n_threads)
     dt = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return dict(value=round(n / dt, 1), unit="events/s", cores=n_threads, kind="oracle",
+                cpu_model=model, nproc=os.cpu_count(),
                 sample=f"first {n} events of the batch, whole path (tracks, ghost-killer, vertices), "
                        f"FP64, {n_threads} threads, {dt:.2f} s wall",
                 single_thread_events_per_s=round(1.0 / per_event, 1))
