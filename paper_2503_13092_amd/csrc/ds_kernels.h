@@ -1224,8 +1224,16 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
                 if (DV1) {
                     r3 = hidx_s[p3];   // Dv1 candidate index: the UTbX hit's index in its run
                 } else {
-                    r3 = first_window_rank(G, hu_s, hidx_s, scs, p3);
-                    if (r3 < 0 || r3 >= G.max_l3) continue;
+                    const int base = s_base[sl];
+                    const int nwin = (sl + 1 < nacc ? s_base[sl + 1] : n_items) - base;
+                    if (CANDS || nwin > G.max_l3) {
+                        r3 = first_window_rank(G, hu_s, hidx_s, scs, p3);
+                        if (r3 < 0 || r3 >= G.max_l3) continue;
+                    } else {
+                        // every window hit is kept: the item's position stands in for its
+                        // rank (it orders only exact ties); phase C ranks the winner
+                        r3 = it - base;
+                    }
                 }
                 if (CANDS) {
                     item_candidates(G, a, hu_s, hidx_s, E, scs, r3, p3,
@@ -1266,6 +1274,15 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
                         for (int it = s_base[tid]; it < b1; ++it)
                             slot = (int)hidx_s[it_desc[it] & 0xffffu] == i3 ? it : slot;
                     }
+                    int cw = c;
+                    if (!DV1) {
+                        const int base = s_base[tid];
+                        const int nwin = (tid + 1 < nacc ? s_base[tid + 1] : n_items) - base;
+                        if (nwin <= G.max_l3) {
+                            const int p3w = (int)(it_desc[base + c / per_r3] & 0xffffu);
+                            cw = first_window_rank(G, hu_s, hidx_s, s_c[tid], p3w) * per_r3 + c % per_r3;
+                        }
+                    }
                     const unsigned long long hp = it_hits[slot];
                     int bp[4];
 #pragma unroll
@@ -1273,7 +1290,7 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
                         const int v = (int)((hp >> (16 * L)) & 0xffffull);
                         bp[L] = v == 0xffff ? -1 : v;
                     }
-                    t = write_track(a, G, i, s_c[tid], hu_s, hidx_s, bp, c);
+                    t = write_track(a, G, i, s_c[tid], hu_s, hidx_s, bp, cw);
                     kept = VTX && t.score < a.score_max;
                 }
             }
