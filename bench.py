@@ -285,8 +285,12 @@ def main():
         ms1 = float(np.mean([e[0].elapsed_time(e[1]) for e in ev_pairs]))
         ev, tr, vt = copies[(args.steps - 1) % len(copies)]
         nh1 = tr.nhits.cpu().numpy()
+        nv1 = int(vt.count.sum().item())
+        ab1 = bpe * E + 24.0 * nv1 + 4.0 * E + 1.0 * batch.n_hits   # + the Y sector byte of every hit
         out["dv1"] = dict(events_per_s=round(E * args.steps / d1, 1), kernel_ms=round(ms1, 4),
-                          tracks=int(np.sum(nh1 > 0)), vertices=int(vt.count.sum().item()),
+                          achieved_GBs=round(ab1 / (ms1 * 1e-3) / 1e9, 2), algorithmic_bytes_per_launch=round(ab1),
+                          traffic=stored_traffic("k_track_fused_dv1", src_hash),
+                          tracks=int(np.sum(nh1 > 0)), vertices=nv1,
                           flags=int(tr.flags.item()) | int(vt.flags.item()),
                           launch="ds_process, algorithm 1: one fused persistent launch, hipGraph replay")
         ctx1.close()
