@@ -51,7 +51,7 @@ struct ds_ctx {
     int *d_counters = nullptr;  // [MAX_STREAM_SLOTS][4]
     std::map<void *, int> slots;
     Launch trk{256, 4, 512};
-    Launch vtx{256, 4, 0};
+    Launch vtx{64, 2, 0};     // measured best for the 10k-event batch (wavefront-per-event kernel)
     hipStream_t capture = nullptr;
     std::map<std::string, GraphEntry> graphs;
     uint64_t tick = 0;
