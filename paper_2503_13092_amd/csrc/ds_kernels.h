@@ -750,11 +750,6 @@ __device__ __forceinline__ void write_candidate_row(const TrackArgs &a, const De
     a.r_chi2[r] = t.chi2;
 }
 
-// Stage one event's hits into LDS, bucketed by (layer, bin); the order inside a
-// bucket is arbitrary (windows select by the full key).  Afterwards E[b] =
-// start of bucket b and E[4*nb] = count.  Hits are read HPT per lane per round
-// with all loads in flight; events of one round keep them in registers
-// between the counting and the placing pass.
 // Bucket of a hit: (layer, u bin) for Dv0; (layer, Y sector, u bin) for Dv1,
 // with one last bucket per layer for sector ids outside [0, nsec).
 template <bool DV1>
@@ -768,90 +763,98 @@ __device__ __forceinline__ int hit_bucket(const TrackArgs &a, int nsec, int L, f
     return b;
 }
 
+constexpr int STAGE_HPT = 16;   // hits per lane per staging round
+
+// Stage one event's hits a wavefront per layer: each wavefront counts its
+// layer's hits into the layer's buckets, scans them (64 buckets per step, DPP
+// sums) and places the hits, with no workgroup barrier until the end: a
+// wavefront's LDS operations complete in order.  Same result as a workgroup
+// counting sort: E[b] = start of bucket b, E[4*nb] = count.  *s_bad must be 0
+// on entry.
 template <int BLOCK, bool DV1, typename Between>
-__device__ __forceinline__ bool stage_hits(const TrackArgs &a, int nsec, int hb, const int hl[4], int nh, float *hu_s,
-                                  uint16_t *hidx_s, int *E, int *s_bad, int *s_wsum, Between &&between)
+__device__ __forceinline__ bool stage_hits_w(const TrackArgs &a, int nsec, int hb, const int hl[4], int nh,
+                                             float *hu_s, uint16_t *hidx_s, int *E, int *s_bad, Between &&between)
 {
-    constexpr int HPT = 16;
-    const int tid = threadIdx.x;
-    const int NBT = 4 * a.nb;
-    const int rounds = (nh + HPT * BLOCK - 1) / (HPT * BLOCK);
+    constexpr int HPT = STAGE_HPT;
+    constexpr int NW = BLOCK / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nb = a.nb;
+    // the first layer's loads are in flight while `between` runs
+    int L = wave;
+    int lo = L < 4 ? hl[L] : 0, n = L < 4 ? (L < 3 ? hl[L + 1] : nh) - hl[L] : 0;
     float u[HPT];
-    // the first round's loads are in flight while the buckets are cleared and
-    // `between` runs (work of the event that needs no hits)
 #pragma unroll
     for (int j = 0; j < HPT; ++j) {
-        const int k = tid + j * BLOCK;
-        u[j] = (k < nh) ? a.hu[hb + k] : 0.0f;
+        const int k = lane + 64 * j;
+        u[j] = (k < n) ? a.hu[hb + lo + k] : 0.0f;
     }
-    for (int k = tid; k <= NBT; k += BLOCK) E[k] = 0;
-    if (tid == 0) *s_bad = 0;
+    if (tid == 0) E[0] = 0;
     between();
-    lds_barrier();
-    for (int r = 0; r < rounds; ++r) {
-        const int k0 = r * HPT * BLOCK + tid;
-        if (r > 0) {
+    bool bad = false;
+    for (; L < 4; L += NW) {
+        if (L != wave) {   // a further layer of this wavefront (fewer than four wavefronts)
+            lo = hl[L];
+            n = (L < 3 ? hl[L + 1] : nh) - lo;
 #pragma unroll
             for (int j = 0; j < HPT; ++j) {
-                const int k = k0 + j * BLOCK;
-                u[j] = (k < nh) ? a.hu[hb + k] : 0.0f;
+                const int k = lane + 64 * j;
+                u[j] = (k < n) ? a.hu[hb + lo + k] : 0.0f;
             }
         }
-        bool bad = false;
+        int *EL = E + 1 + L * nb;   // EL[b]: count, then end, of bucket (L, b)
+        for (int b = lane; b < nb; b += 64) EL[b] = 0;
+        const int rounds = (n + 64 * HPT - 1) / (64 * HPT);
+        for (int r = 0; r < rounds; ++r) {
+            if (r > 0) {
 #pragma unroll
-        for (int j = 0; j < HPT; ++j) {
-            if ((r * HPT + j) * BLOCK >= nh) break;   // uniform: no lane has slot j
-            const int k = k0 + j * BLOCK;
-            if (k < nh) {
-                if (!isfinite(u[j])) {
-                    bad = true;
-                } else {
-                    const int L = (k >= hl[1]) + (k >= hl[2]) + (k >= hl[3]);
-                    atomicAdd(&E[hit_bucket<DV1>(a, nsec, L, u[j], hb + k) + 1], 1);
+                for (int j = 0; j < HPT; ++j) {
+                    const int k = r * 64 * HPT + lane + 64 * j;
+                    u[j] = (k < n) ? a.hu[hb + lo + k] : 0.0f;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < HPT; ++j) {
+                if (r * 64 * HPT + 64 * j >= n) break;   // uniform: no lane has slot j
+                const int k = r * 64 * HPT + lane + 64 * j;
+                if (k < n) {
+                    if (!isfinite(u[j])) bad = true;
+                    else atomicAdd(&E[hit_bucket<DV1>(a, nsec, L, u[j], hb + lo + k) + 1], 1);
                 }
             }
         }
-        if (bad) *s_bad = 1;
-    }
-    lds_barrier();
-    if (*s_bad) return false;
-    // exclusive scan of the bucket counts held at E[1..NBT]: E[b + 1] = start of bucket b
-    const int per = (NBT + BLOCK - 1) / BLOCK;
-    const int j_end = min(per, NBT - tid * per);   // may be <= 0 for the last lanes
-    int local = 0;
-    for (int j = 0; j < j_end; ++j) local += E[1 + tid * per + j];
-    int tot;
-    int run = block_exclusive_scan<BLOCK>(local, s_wsum, &tot);
-    for (int j = 0; j < j_end; ++j) {
-        const int cnt = E[1 + tid * per + j];
-        E[1 + tid * per + j] = run;
-        run += cnt;
-    }
-    lds_barrier();
-    // placing pass: E[b + 1] advances to the end of bucket b = start of bucket b + 1
-    for (int r = 0; r < rounds; ++r) {
-        const int k0 = r * HPT * BLOCK + tid;
-        if (rounds > 1) {
+        // exclusive prefix over the layer's buckets, offset by the layer's start
+        int carry = lo;
+        for (int b0 = 0; b0 < nb; b0 += 64) {
+            const int b = b0 + lane;
+            const int v = b < nb ? EL[b] : 0;
+            const int incl = wave_inclusive_sum(v);
+            if (b < nb) EL[b] = carry + incl - v;
+            carry += __builtin_amdgcn_readlane(incl, 63);
+        }
+        // placing pass: EL[b] advances to the end of bucket b
+        for (int r = 0; r < rounds; ++r) {
+            if (rounds > 1) {
+#pragma unroll
+                for (int j = 0; j < HPT; ++j) {
+                    const int k = r * 64 * HPT + lane + 64 * j;
+                    u[j] = (k < n) ? a.hu[hb + lo + k] : 0.0f;
+                }
+            }
 #pragma unroll
             for (int j = 0; j < HPT; ++j) {
-                const int k = k0 + j * BLOCK;
-                u[j] = (k < nh) ? a.hu[hb + k] : 0.0f;
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < HPT; ++j) {
-            if ((r * HPT + j) * BLOCK >= nh) break;   // uniform: no lane has slot j
-            const int k = k0 + j * BLOCK;
-            if (k < nh) {
-                const int L = (k >= hl[1]) + (k >= hl[2]) + (k >= hl[3]);
-                const int pos = atomicAdd(&E[hit_bucket<DV1>(a, nsec, L, u[j], hb + k) + 1], 1);
-                hu_s[pos] = u[j];
-                hidx_s[pos] = (uint16_t)(k - hl[L]);
+                if (r * 64 * HPT + 64 * j >= n) break;
+                const int k = r * 64 * HPT + lane + 64 * j;
+                if (k < n && isfinite(u[j])) {
+                    const int pos = atomicAdd(&E[hit_bucket<DV1>(a, nsec, L, u[j], hb + lo + k) + 1], 1);
+                    hu_s[pos] = u[j];
+                    hidx_s[pos] = (uint16_t)k;
+                }
             }
         }
     }
+    if (bad) *s_bad = 1;
     lds_barrier();
-    return true;
+    return *s_bad == 0;
 }
 
 __device__ __forceinline__ void unrank_pair(int k, int n, int &pa, int &pb);
@@ -1017,6 +1020,7 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
         int ho[5];
 #pragma unroll
         for (int L = 0; L < 5; ++L) ho[L] = s_nx[3 + L];
+        if (tid == 0) s_bad = 0;
         lds_barrier();   // s_nx read by every wave before it is refilled
         const bool seeds_ok = (0 <= s0) && (s0 <= s1) && (s1 <= a.n_seeds);
         bool hits_ok = (0 <= ho[0]) && (ho[4] <= a.n_hits);
@@ -1060,7 +1064,7 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
                 s_c[tid] = sc;
             }
         };
-        if (!stage_hits<BLOCK, DV1>(a, G.nsec, ho[0], hl, nh, hu_s, hidx_s, E, &s_bad, s_wsum, first_frames)) {
+        if (!stage_hits_w<BLOCK, DV1>(a, G.nsec, ho[0], hl, nh, hu_s, hidx_s, E, &s_bad, first_frames)) {
             if (tid == 0) atomicOr(a.flags, F_NONFINITE);
             if (VTX && tid == 0) a.vcount[e] = 0;
             for (int i = s0 + tid; i < s1; i += BLOCK) write_empty_track(a, i);

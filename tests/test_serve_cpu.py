@@ -113,4 +113,5 @@ def test_latency_is_from_scheduled_arrival(pool):
     srv = serve.Server(be, pool)
     arr = np.arange(1, 21) * 0.02    # far apart: every event waits only for its own service
     lat, st = srv.run(arr, warmup_frac=0.0)
-    assert np.all(lat >= 5e-3) and np.median(lat) < 5e-3 + 3e-3
+    # at least the service time; well under the 20 ms spacing (host scheduling noise allowed)
+    assert np.all(lat >= 5e-3) and np.median(lat) < 5e-3 + 12e-3
