@@ -46,7 +46,7 @@ struct ds_ctx {
     double ghost_threshold = 0.5;
     bool clone_kill = false;
     int algorithm = 0;             // 0: Dv0 window search, 1: Dv1 triplet search
-    float *d_W = nullptr;
+    float *d_W = nullptr;    // ghost-killer weights, per-lane MFMA order (mlp_lane_layout)
     float *d_WL = nullptr;   // trigger-line networks
     int *d_counters = nullptr;  // [MAX_STREAM_SLOTS][4]
     std::map<void *, int> slots;
@@ -607,8 +607,12 @@ ds_status ds_load_geometry(ds_ctx *c, const ds_geometry *g, const float *w, size
     G.sec_y0 = g->sector_y0;
     G.sec_h = g->algorithm == 1 ? g->sector_h : 1.0;
     G.sec_tol = g->sector_tol;
-    if (!c->d_W && hipMalloc(&c->d_W, sizeof(float) * ds::NWEIGHTS) != hipSuccess) return DS_E_NOMEM;
-    if (hipMemcpy(c->d_W, w, sizeof(float) * ds::NWEIGHTS, hipMemcpyHostToDevice) != hipSuccess)
+    // the ghost-killer network is evaluated on the matrix cores: its weights go
+    // to the device in the per-lane order of the MFMA operands
+    std::vector<float> wm(ds::MLP_WM);
+    ds::mlp_lane_layout(w, wm.data());
+    if (!c->d_W && hipMalloc(&c->d_W, sizeof(float) * ds::MLP_WM) != hipSuccess) return DS_E_NOMEM;
+    if (hipMemcpy(c->d_W, wm.data(), sizeof(float) * ds::MLP_WM, hipMemcpyHostToDevice) != hipSuccess)
         return DS_E_DEVICE;
     c->G = G;
     c->u_min = g->u_min;

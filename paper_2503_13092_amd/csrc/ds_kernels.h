@@ -29,6 +29,38 @@ namespace ds {
 
 constexpr int NF = 17, NH1 = 32, NH2 = 16;
 constexpr int NWEIGHTS = NH1 * NF + NH1 + NH2 * NH1 + NH2 + NH2 + 1;  // 1121
+// Per-lane weight words of mlp_score_wave (lane l, group g = l / 16, n = l % 16):
+// [u * 5 + s] = W1[16 u + n][4 s + g] (b1 in input column 17, zeros past it),
+// [MLP_A2 + 4 u + r] = W2[n][16 u + 4 g + r], [MLP_B2 + r] = b2[4 g + r],
+// [MLP_W3 + r] = W3[4 g + r], [MLP_B3] = b3; stored as float4 q of lane l at
+// (q * 64 + l).
+constexpr int MLP_K1 = 20, MLP_A2 = 10, MLP_B2 = 18, MLP_W3 = 22, MLP_B3 = 26;
+constexpr int MLP_LANE_WORDS = 28;
+constexpr int MLP_WM = 64 * MLP_LANE_WORDS;
+
+// Host side: the per-lane order from the row-major parameters W1, b1, W2, b2, W3, b3.
+inline void mlp_lane_layout(const float *w, float *wm)
+{
+    const float *W1 = w, *b1 = W1 + NH1 * NF, *W2 = b1 + NH1, *b2 = W2 + NH2 * NH1, *W3 = b2 + NH2, *b3 = W3 + NH2;
+    for (int l = 0; l < 64; ++l) {
+        const int g = l / 16, n = l % 16;
+        float v[MLP_LANE_WORDS] = {};
+        for (int u = 0; u < 2; ++u)
+            for (int s = 0; s < MLP_K1 / 4; ++s) {
+                const int j = 16 * u + n, k = 4 * s + g;
+                v[u * (MLP_K1 / 4) + s] = k < NF ? W1[j * NF + k] : (k == NF ? b1[j] : 0.0f);
+            }
+        for (int u = 0; u < 2; ++u)
+            for (int r = 0; r < 4; ++r) v[MLP_A2 + 4 * u + r] = W2[n * NH1 + 16 * u + 4 * g + r];
+        for (int r = 0; r < 4; ++r) {
+            v[MLP_B2 + r] = b2[4 * g + r];
+            v[MLP_W3 + r] = W3[4 * g + r];
+        }
+        v[MLP_B3] = b3[0];
+        for (int k = 0; k < MLP_LANE_WORDS; ++k) wm[((k / 4) * 64 + l) * 4 + k % 4] = v[k];
+    }
+}
+
 constexpr int MAX_L3 = 16;
 constexpr int MAX_CLOSEST = 2;
 constexpr int F_BAD_OFFSETS = 1, F_CAPACITY = 2, F_NONFINITE = 4;
@@ -340,32 +372,103 @@ __device__ __forceinline__ void ghost_features(const DevGeom &G, float xf, float
 typedef const __attribute__((address_space(4))) float cfloat;
 
 // 17 -> 32 ReLU -> 16 ReLU -> 1 sigmoid, float32 FMA; W is wave-uniform.
-__device__ __forceinline__ float mlp_score(const float *Wg, const float f[NF])
+// The ghost-killer network ("Ghost-Killer Neural Network": 17 inputs, ReLU
+// hidden layers of 32 and 16, sigmoid output) of a wavefront's 64 rows, one
+// row per lane, on the matrix cores.  Both hidden layers are products
+// H^T = W X^T of v_mfma_f32_16x16x4_f32 tiles: 16 units x 16 rows per tile,
+// 4 inputs per step.  In a tile, lane l holds row (l % 16) of its block and
+// input / unit index 4 (l / 16) + r, so a lane's own 17 features are first
+// transposed across the four 16-lane groups (permlane swaps), and the layer-1
+// output is already in the layer-2 operand layout.  The weights come in the
+// per-lane order built by mlp_lane_layout.  Every output element is the same
+// sequence of operations wherever its row sits, so a track's score does not
+// depend on its lane.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// lanes 32..63 of a <-> lanes 0..31 of b
+__device__ __forceinline__ void lane_swap32(float &a, float &b)
 {
-    // opaque to the optimiser: keeps the scalar weight loads next to their
-    // uses instead of hoisting 1121 values out of the event loop into spills
-    asm volatile("" : "+s"(Wg));
-    cfloat *W = (cfloat *)(Wg);
-    cfloat *W1 = W, *b1 = W + NH1 * NF, *W2 = b1 + NH1, *b2 = W2 + NH2 * NH1, *W3 = b2 + NH2, *b3 = W3 + NH2;
-    // hidden layer 1 is consumed as it is produced: h2[k] accumulates
-    // W2[k][j] * h1[j] in increasing j, the same order as a full h1 vector
-    float h2[NH2];
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+
+// odd 16-lane groups of a <-> even 16-lane groups of b
+__device__ __forceinline__ void lane_swap16(float &a, float &b)
+{
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+
+// This lane's weight words of mlp_score_wave.
+__device__ __forceinline__ void mlp_lane_weights(const float *Wm, float w[MLP_LANE_WORDS])
+{
+    const int lane = threadIdx.x & 63;
+    const float4 *W4 = reinterpret_cast<const float4 *>(Wm);
 #pragma unroll
-    for (int k = 0; k < NH2; ++k) h2[k] = b2[k];
-#pragma unroll
-    for (int j = 0; j < NH1; ++j) {
-        float a = b1[j];
-#pragma unroll
-        for (int k = 0; k < NF; ++k) a = fmaf(W1[j * NF + k], f[k], a);
-        const float h1j = fmaxf(a, 0.0f);
-#pragma unroll
-        for (int k = 0; k < NH2; ++k) h2[k] = fmaf(W2[k * NH1 + j], h1j, h2[k]);
+    for (int q = 0; q < MLP_LANE_WORDS / 4; ++q) {
+        const float4 v = W4[q * 64 + lane];
+        w[4 * q] = v.x;
+        w[4 * q + 1] = v.y;
+        w[4 * q + 2] = v.z;
+        w[4 * q + 3] = v.w;
     }
+}
+
+// All 64 lanes must call it together (wave-uniform control flow).  Lanes with
+// row == false contribute zeros; every lane gets its own row's score.
+__device__ __forceinline__ float mlp_score_wave(const float w[MLP_LANE_WORDS], const float f[NF], bool row)
+{
+    const int lane = threadIdx.x & 63, grp = lane >> 4;
+    const unsigned long long rows = __ballot(row);
+    // layer-1 inputs padded to 20: the features, 1 (the bias column), zeros
+    float x[MLP_K1];
 #pragma unroll
-    for (int k = 0; k < NH2; ++k) h2[k] = fmaxf(h2[k], 0.0f);
-    float z = b3[0];
+    for (int k = 0; k < MLP_K1; ++k) x[k] = (row && k < NF) ? f[k] : (row && k == NF) ? 1.0f : 0.0f;
+    // per step s, (register 4s + j, group b) -> (register 4s + b, group j): then
+    // x[4s + b] holds, in group j, input 4s + j of the row of lane 16 b + l % 16
 #pragma unroll
-    for (int k = 0; k < NH2; ++k) z = fmaf(W3[k], h2[k], z);
+    for (int s = 0; s < MLP_K1 / 4; ++s) {
+        lane_swap32(x[4 * s], x[4 * s + 2]);
+        lane_swap32(x[4 * s + 1], x[4 * s + 3]);
+        lane_swap16(x[4 * s], x[4 * s + 1]);
+        lane_swap16(x[4 * s + 2], x[4 * s + 3]);
+    }
+    float z = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        if (((rows >> (16 * b)) & 0xffffull) == 0) continue;   // no row in this block
+        f32x4 h[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            h[u] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int s = 0; s < MLP_K1 / 4; ++s)
+                h[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(w[u * (MLP_K1 / 4) + s], x[4 * s + b], h[u], 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) h[u][r] = fmaxf(h[u][r], 0.0f);
+        }
+        f32x4 o = f32x4{w[MLP_B2], w[MLP_B2 + 1], w[MLP_B2 + 2], w[MLP_B2 + 3]};
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                o = __builtin_amdgcn_mfma_f32_16x16x4f32(w[MLP_A2 + 4 * u + r], h[u][r], o, 0, 0, 0);
+        float p = 0.0f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) p = fmaf(w[MLP_W3 + r], fmaxf(o[r], 0.0f), p);
+        // sum over the four groups: (g0 + g2) + (g1 + g3), in every group
+        float c = p, d = p;
+        lane_swap32(c, d);
+        const float p2 = c + d;
+        c = p2;
+        d = p2;
+        lane_swap16(c, d);
+        const float zb = c + d;
+        z = grp == b ? zb : z;
+    }
+    z += w[MLP_B3];
     return 1.0f / (1.0f + __expf(-z));
 }
 
@@ -667,15 +770,27 @@ __device__ __forceinline__ void item_best(const DevGeom &G, const TrackArgs &a, 
                     });
 }
 
-// The float32 track record of a fitted candidate and (optionally) its ghost score.
+// The float32 track record of a fitted candidate; its ghost score is set by
+// the caller (mlp_score_wave of the features, 0 without the network).
 struct StoredTrack {
     float x, y, tx, ty, qop, chi2, score;
 };
 
-__device__ __forceinline__ StoredTrack stored_track(const TrackArgs &a, const DevGeom &G, int i, int n, double al, double be,
-                                           double c2, const float *hu_s, const int bp[4], bool score)
+// A seed's float32 parameters.
+struct SeedRaw {
+    float x, y, tx, ty, qop;
+};
+
+__device__ __forceinline__ SeedRaw load_seed(const TrackArgs &a, int i)
 {
-    const float fsx = a.sx[i], fsy = a.sy[i], fstx = a.stx[i], fsty = a.sty[i], fsq = a.sqop[i];
+    return SeedRaw{a.sx[i], a.sy[i], a.stx[i], a.sty[i], a.sqop[i]};
+}
+
+// f (optional): the track's ghost-killer features.
+__device__ __forceinline__ StoredTrack stored_track(const DevGeom &G, const SeedRaw &sd, int n, double al, double be,
+                                           double c2, const float *hu_s, const int bp[4], float *f)
+{
+    const float fsx = sd.x, fsy = sd.y, fstx = sd.tx, fsty = sd.ty, fsq = sd.qop;
     const double sx = fsx, sy = fsy, stx = fstx, sty = fsty;
     StoredTrack t;
     t.x = (float)(fma(stx, G.zref_seed, sx) + al);
@@ -685,7 +800,7 @@ __device__ __forceinline__ StoredTrack stored_track(const TrackArgs &a, const De
     t.qop = (G.mk != 0.0) ? (float)(-be / G.mk) : fsq;
     t.chi2 = (float)c2;
     t.score = 0.0f;
-    if (score) {
+    if (f) {
         float hu4[4];
         int mask = 0;
 #pragma unroll
@@ -693,16 +808,16 @@ __device__ __forceinline__ StoredTrack stored_track(const TrackArgs &a, const De
             hu4[L] = bp[L] >= 0 ? hu_s[bp[L]] : 0.0f;
             mask |= bp[L] >= 0 ? (1 << L) : 0;
         }
-        float f[NF];
         ghost_features(G, t.x, t.y, t.tx, t.ty, t.qop, t.chi2, n, fsx, fsy, fstx, fsty, fsq, hu4, mask, f);
-        t.score = mlp_score(a.W, f);
     }
     return t;
 }
 
-// Write the selected candidate (LDS positions bp, -1 = none) as seed i's track.
-__device__ __forceinline__ StoredTrack write_track(const TrackArgs &a, const DevGeom &G, int i, const SeedConst &sc,
-                                          const float *hu_s, const uint16_t *hidx_s, const int bp[4], int c)
+// Write the selected candidate (LDS positions bp, -1 = none) as seed i's
+// track, all but its ghost score; f (optional) receives its features.
+__device__ __forceinline__ StoredTrack write_track(const TrackArgs &a, const DevGeom &G, int i, const SeedRaw &sd,
+                                          const SeedConst &sc, const float *hu_s, const uint16_t *hidx_s, const int bp[4],
+                                          int c, float *f)
 {
     const int mask = (bp[0] >= 0 ? 1 : 0) | (bp[1] >= 0 ? 2 : 0) | (bp[2] >= 0 ? 4 : 0) | 8;
     const int n = __popc(mask);
@@ -711,7 +826,7 @@ __device__ __forceinline__ StoredTrack write_track(const TrackArgs &a, const Dev
     for (int L = 0; L < 4; ++L) rho[L] = bp[L] >= 0 ? (double)hu_s[bp[L]] - sc.c[L] : 0.0;
     double al, be, c2;
     fit_set(G, fit_const(G, mask), rho, al, be, c2);
-    const StoredTrack t = stored_track(a, G, i, n, al, be, c2, hu_s, bp, a.fuse_mlp != 0);
+    const StoredTrack t = stored_track(G, sd, n, al, be, c2, hu_s, bp, f);
     a.x[i] = t.x;
     a.y[i] = t.y;
     a.tx[i] = t.tx;
@@ -724,7 +839,6 @@ __device__ __forceinline__ StoredTrack write_track(const TrackArgs &a, const Dev
     a.h3[i] = (int)hidx_s[bp[3]];
     a.nhits[i] = n;
     if (a.cand) a.cand[i] = c;
-    if (a.fuse_mlp) a.score[i] = t.score;
     return t;
 }
 
@@ -733,7 +847,7 @@ __device__ __forceinline__ void write_candidate_row(const TrackArgs &a, const De
                                            double be, double c2, const float *hu_s, const uint16_t *hidx_s,
                                            const int bp[4])
 {
-    const StoredTrack t = stored_track(a, G, i, n, al, be, c2, hu_s, bp, false);
+    const StoredTrack t = stored_track(G, load_seed(a, i), n, al, be, c2, hu_s, bp, nullptr);
     const size_t r = (size_t)i * (size_t)a.cmax + (size_t)c;
     a.r_seed[r] = i;
     a.r_cand[r] = c;
@@ -822,14 +936,28 @@ __device__ __forceinline__ bool stage_hits_w(const TrackArgs &a, int nsec, int h
                 }
             }
         }
-        // exclusive prefix over the layer's buckets, offset by the layer's start
+        // exclusive prefix over the layer's buckets, offset by the layer's start;
+        // up to 512 buckets: eight independent wavefront scans, then the carries
         int carry = lo;
-        for (int b0 = 0; b0 < nb; b0 += 64) {
-            const int b = b0 + lane;
-            const int v = b < nb ? EL[b] : 0;
-            const int incl = wave_inclusive_sum(v);
-            if (b < nb) EL[b] = carry + incl - v;
-            carry += __builtin_amdgcn_readlane(incl, 63);
+        if (nb <= 512) {
+            int v[8], incl[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = 64 * j + lane < nb ? EL[64 * j + lane] : 0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) incl[j] = wave_inclusive_sum(v[j]);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (64 * j + lane < nb) EL[64 * j + lane] = carry + incl[j] - v[j];
+                carry += __builtin_amdgcn_readlane(incl[j], 63);
+            }
+        } else {
+            for (int b0 = 0; b0 < nb; b0 += 64) {
+                const int b = b0 + lane;
+                const int v1 = b < nb ? EL[b] : 0;
+                const int incl1 = wave_inclusive_sum(v1);
+                if (b < nb) EL[b] = carry + incl1 - v1;
+                carry += __builtin_amdgcn_readlane(incl1, 63);
+            }
         }
         // placing pass: EL[b] advances to the end of bucket b
         for (int r = 0; r < rounds; ++r) {
@@ -970,7 +1098,7 @@ __device__ __forceinline__ void fetch_event(const TrackArgs &a, int iter, int la
 }
 
 template <int BLOCK, bool CANDS, bool VTX, bool DV1>
-__global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2 : 3))) void k_track(TrackKernArgs)
 {
     static_assert(!(CANDS && DV1), "candidate rows follow Dv0");
     const TrackArgs &a0 = kernel_args<TrackKernArgs>().a;
@@ -1258,10 +1386,16 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
                     atomicMin(&s_key[sl], DV1 ? pack_key_dv1(bn, bchi2, bc) : pack_key(bn, bchi2, bc));
                 }
             }
+            // the seed parameters of phase C are loaded before the barrier: their
+            // latency overlaps the wait
+            SeedRaw sd{};
+            if (!CANDS && tid < nacc) sd = load_seed(a, i);
             lds_barrier();
-            // phase C: lane per seed, write the winner (and its ghost score)
-            bool kept = false;
+            // phase C: lane per seed, write the winner; then its ghost score, the
+            // network run by each wavefront with a winner as a whole
+            bool won = false;
             StoredTrack t;
+            float f[NF];
             if (!CANDS && tid < nacc) {
                 const int per_r3 = G.nw[0] * G.nw[1] * G.nw[2];
                 const unsigned long long key = s_key[tid];
@@ -1294,10 +1428,20 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
                         const int v = (int)((hp >> (16 * L)) & 0xffffull);
                         bp[L] = v == 0xffff ? -1 : v;
                     }
-                    t = write_track(a, G, i, s_c[tid], hu_s, hidx_s, bp, cw);
-                    kept = VTX && t.score < a.score_max;
+                    t = write_track(a, G, i, sd, s_c[tid], hu_s, hidx_s, bp, cw, a.fuse_mlp ? f : nullptr);
+                    won = true;
                 }
             }
+            if (!CANDS && a.fuse_mlp && __ballot(won) != 0) {
+                float mw[MLP_LANE_WORDS];
+                mlp_lane_weights(a.W, mw);
+                const float sc_ = mlp_score_wave(mw, f, won);
+                if (won) {
+                    t.score = sc_;
+                    a.score[i] = sc_;
+                }
+            }
+            const bool kept = VTX && won && t.score < a.score_max;
             if (VTX) {
                 // kept tracks appended in slot order
                 int ktot;
@@ -1306,7 +1450,7 @@ __global__ __launch_bounds__(BLOCK) void k_track(TrackKernArgs)
                     const int k = s_nkept + kpos;
                     kst[k] = make_float4(t.x, t.y, t.tx, t.ty);
                     kq[k] = t.qop;
-                    kslot[k] = ((i - s0) << 1) | (a.sqop[i] > 0.0f ? 1 : 0);
+                    kslot[k] = ((i - s0) << 1) | (sd.qop > 0.0f ? 1 : 0);
                 }
                 lds_barrier();
                 if (tid == 0) s_nkept += ktot;
@@ -1351,25 +1495,33 @@ __global__ __launch_bounds__(256) void k_score_rows(TrackArgs a, DevGeom G)
         for (int L = 0; L < 4; ++L) ok = ok && (ho[L] <= ho[L + 1]);
         if (!ok) continue;
         const long long r0 = (long long)s0 * a.cmax, r1 = (long long)s1 * a.cmax;
-        for (long long r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-            const int nh = a.r_nhits[r];
-            if (nh <= 0) continue;
-            const int i = (int)(r / a.cmax);
-            const int hh[4] = {a.r_h0[r], a.r_h1[r], a.r_h2[r], a.r_h3[r]};
-            float hu4[4];
-            int has = 0;
-#pragma unroll
-            for (int L = 0; L < 4; ++L) {
-                hu4[L] = 0.0f;
-                if (hh[L] >= 0 && hh[L] < ho[L + 1] - ho[L]) {
-                    hu4[L] = a.hu[ho[L] + hh[L]];
-                    has |= 1 << L;
-                }
-            }
+        // uniform trip count: the network runs on whole wavefronts
+        for (long long rb = r0; rb < r1; rb += blockDim.x) {
+            const long long r = rb + threadIdx.x;
+            const int nh = r < r1 ? a.r_nhits[r] : 0;
             float f[NF];
-            ghost_features(G, a.r_x[r], a.r_y[r], a.r_tx[r], a.r_ty[r], a.r_qop[r], a.r_chi2[r], nh, a.sx[i], a.sy[i],
-                           a.stx[i], a.sty[i], a.sqop[i], hu4, has, f);
-            a.r_score[r] = mlp_score(a.W, f);
+            if (nh > 0) {
+                const int i = (int)(r / a.cmax);
+                const int hh[4] = {a.r_h0[r], a.r_h1[r], a.r_h2[r], a.r_h3[r]};
+                float hu4[4];
+                int has = 0;
+#pragma unroll
+                for (int L = 0; L < 4; ++L) {
+                    hu4[L] = 0.0f;
+                    if (hh[L] >= 0 && hh[L] < ho[L + 1] - ho[L]) {
+                        hu4[L] = a.hu[ho[L] + hh[L]];
+                        has |= 1 << L;
+                    }
+                }
+                ghost_features(G, a.r_x[r], a.r_y[r], a.r_tx[r], a.r_ty[r], a.r_qop[r], a.r_chi2[r], nh, a.sx[i],
+                               a.sy[i], a.stx[i], a.sty[i], a.sqop[i], hu4, has, f);
+            }
+            if (__ballot(nh > 0) != 0) {
+                float mw[MLP_LANE_WORDS];
+                mlp_lane_weights(a.W, mw);
+                const float sc = mlp_score_wave(mw, f, nh > 0);
+                if (nh > 0) a.r_score[r] = sc;
+            }
         }
     }
 }
@@ -1390,37 +1542,43 @@ __global__ __launch_bounds__(BLOCK) void k_ghost(GhostArgs a, DevGeom G)
             if (threadIdx.x == 0) atomicOr(a.flags, F_BAD_OFFSETS);
             continue;
         }
-        for (int i = s0 + (int)threadIdx.x; i < s1; i += BLOCK) {
-            const int nh = a.nhits[i];
-            if (nh <= 0) {
-                a.score[i] = 0.0f;
-                continue;
-            }
-            const int hh[4] = {a.h0[i], a.h1[i], a.h2[i], a.h3[i]};
-            float hu4[4];
-            int has = 0;
-            bool hit_ok = true;
+        // uniform trip count: the network runs on whole wavefronts
+        for (int ib = s0; ib < s1; ib += BLOCK) {
+            const int i = ib + (int)threadIdx.x;
+            bool row = false;
+            float f[NF];
+            if (i < s1) {
+                const int nh = a.nhits[i];
+                const int hh[4] = {a.h0[i], a.h1[i], a.h2[i], a.h3[i]};
+                float hu4[4];
+                int has = 0;
+                bool hit_ok = true;
 #pragma unroll
-            for (int L = 0; L < 4; ++L) {
-                hu4[L] = 0.0f;
-                if (hh[L] >= 0) {
-                    if (hh[L] < ho[L + 1] - ho[L]) {
-                        hu4[L] = a.hu[ho[L] + hh[L]];
-                        has |= 1 << L;
-                    } else {
-                        hit_ok = false;
+                for (int L = 0; L < 4; ++L) {
+                    hu4[L] = 0.0f;
+                    if (hh[L] >= 0) {
+                        if (hh[L] < ho[L + 1] - ho[L]) {
+                            hu4[L] = a.hu[ho[L] + hh[L]];
+                            has |= 1 << L;
+                        } else {
+                            hit_ok = false;
+                        }
                     }
                 }
+                if (nh > 0 && !hit_ok) atomicOr(a.flags, F_BAD_OFFSETS);
+                row = nh > 0 && hit_ok;
+                if (row)
+                    ghost_features(G, a.x[i], a.y[i], a.tx[i], a.ty[i], a.qop[i], a.chi2[i], nh, a.sx[i], a.sy[i],
+                                   a.stx[i], a.sty[i], a.sqop[i], hu4, has, f);
+                else
+                    a.score[i] = 0.0f;
             }
-            if (!hit_ok) {
-                atomicOr(a.flags, F_BAD_OFFSETS);
-                a.score[i] = 0.0f;
-                continue;
+            if (__ballot(row) != 0) {
+                float mw[MLP_LANE_WORDS];
+                mlp_lane_weights(a.W, mw);
+                const float sc = mlp_score_wave(mw, f, row);
+                if (row) a.score[i] = sc;
             }
-            float f[NF];
-            ghost_features(G, a.x[i], a.y[i], a.tx[i], a.ty[i], a.qop[i], a.chi2[i], nh, a.sx[i], a.sy[i], a.stx[i],
-                           a.sty[i], a.sqop[i], hu4, has, f);
-            a.score[i] = mlp_score(a.W, f);
         }
     }
 }
