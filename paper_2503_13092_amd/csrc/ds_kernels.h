@@ -561,43 +561,97 @@ __device__ __forceinline__ void sector_span(const SeedConst &sc, int L, int &klo
 }
 
 // LDS ranges of the buckets of layer L, sectors klo..khi (at most two), whose
-// u bins cover [m - W, m + W]; buckets are (layer, sector, u bin).
-__device__ __forceinline__ void sector_bins(const int *E, const TrackArgs &a, int L, int klo, int khi, double m, double W,
-                                   int &lo0, int &len0, int &lo1, int &len1)
+// u bins cover [m - W, m + W]; buckets are (layer, sector, u bin).  Branch-free:
+// the four bounds are read at sector indices clamped into the layer's buckets
+// and dropped when the sector is not in the span.
+__device__ __forceinline__ void sector_bins(const int *E, const TrackArgs &a, int nsec, int L, int klo, int khi, double m,
+                                   double W, int &lo0, int &len0, int &lo1, int &len1)
 {
     const int b_lo = bin_of((float)(m - W - 1e-3), a.u0, a.inv_bw, a.nbu);
     const int b_hi = bin_of((float)(m + W + 1e-3), a.u0, a.inv_bw, a.nbu);
-    lo0 = len0 = lo1 = len1 = 0;
-    if (klo <= khi) {
-        const int base = L * a.nb + klo * a.nbu;
-        lo0 = E[base + b_lo];
-        len0 = E[base + b_hi + 1] - lo0;
-    }
-    if (klo + 1 <= khi) {
-        const int base = L * a.nb + (klo + 1) * a.nbu;
-        lo1 = E[base + b_lo];
-        len1 = E[base + b_hi + 1] - lo1;
-    }
+    const int base0 = L * a.nb + min(klo, nsec - 1) * a.nbu, base1 = L * a.nb + min(klo + 1, nsec - 1) * a.nbu;
+    const int e0 = E[base0 + b_lo], e1 = E[base0 + b_hi + 1], e2 = E[base1 + b_lo], e3 = E[base1 + b_hi + 1];
+    const bool in0 = klo <= khi, in1 = klo + 1 <= khi;
+    lo0 = in0 ? e0 : 0;
+    len0 = in0 ? e1 - e0 : 0;
+    lo1 = in1 ? e2 : 0;
+    len1 = in1 ? e3 - e2 : 0;
 }
 
 // Does the line through the magnet point and the UTbX hit at p3 meet a UTaX
-// hit of a compatible sector within W (the axial triplet)?
+// hit of a compatible sector within W (the axial triplet)?  In two parts: the
+// probe of the first two UTaX positions (most probes look at <= 2 hits),
+// straight-line so that two seeds' probes can overlap, then the rest.
+constexpr int DV1_PROBE = 4;   // window positions read by the paired probe
+
+struct TripletProbe {
+    double m0;
+    int lo0, len0, lo1, len1;
+    bool hit;
+};
+
+__device__ __forceinline__ TripletProbe dv1_probe(const DevGeom &G, const TrackArgs &a, const float *hu_s, const int *E,
+                                         const SeedConst &sc, int k0lo, int k0hi, double W, int p3)
+{
+    TripletProbe t;
+    t.m0 = fma((double)hu_s[p3] - sc.c[3], G.ffac[0], sc.c[0]);
+    sector_bins(E, a, G.nsec, 0, k0lo, k0hi, t.m0, W, t.lo0, t.len0, t.lo1, t.len1);
+    const int n = t.len0 + t.len1;
+    const int pa = t.len0 > 0 ? t.lo0 : t.lo1, pb = t.len0 > 1 ? t.lo0 + 1 : (t.len0 == 1 ? t.lo1 : t.lo1 + 1);
+    const float ua = hu_s[n > 0 ? pa : 0], ub = hu_s[n > 1 ? pb : 0];
+    // bitwise, not short-circuit: no branch between the reads and the tests
+    t.hit = ((n > 0) & (fabs((double)ua - t.m0) <= W)) | ((n > 1) & (fabs((double)ub - t.m0) <= W));
+    return t;
+}
+
+// Probes of two (seed, UTbX hit) pairs, stage by stage (the hits' u, the
+// projections, the eight bucket bounds, the first four UTaX positions of each
+// window), so that each stage costs one LDS round trip for both; a window
+// holding more than four hits is finished by dv1_rest.
+__device__ __forceinline__ void dv1_probe_pair(const DevGeom &G, const TrackArgs &a, const float *hu_s, const int *E,
+                                      const SeedConst &sa, const SeedConst &sb, int ka_lo, int ka_hi, int kb_lo,
+                                      int kb_hi, double Wa, double Wb, int pa3, int pb3, TripletProbe &ta,
+                                      TripletProbe &tb)
+{
+    const float ua3 = hu_s[pa3], ub3 = hu_s[pb3];
+    ta.m0 = fma((double)ua3 - sa.c[3], G.ffac[0], sa.c[0]);
+    tb.m0 = fma((double)ub3 - sb.c[3], G.ffac[0], sb.c[0]);
+    sector_bins(E, a, G.nsec, 0, ka_lo, ka_hi, ta.m0, Wa, ta.lo0, ta.len0, ta.lo1, ta.len1);
+    sector_bins(E, a, G.nsec, 0, kb_lo, kb_hi, tb.m0, Wb, tb.lo0, tb.len0, tb.lo1, tb.len1);
+    const int na = ta.len0 + ta.len1, nb = tb.len0 + tb.len1;
+    float va[DV1_PROBE], vb[DV1_PROBE];
+#pragma unroll
+    for (int k = 0; k < DV1_PROBE; ++k) {
+        const int qa = k < ta.len0 ? ta.lo0 + k : ta.lo1 + (k - ta.len0);
+        const int qb = k < tb.len0 ? tb.lo0 + k : tb.lo1 + (k - tb.len0);
+        va[k] = hu_s[k < na ? qa : 0];
+        vb[k] = hu_s[k < nb ? qb : 0];
+    }
+    bool ha = false, hb = false;
+#pragma unroll
+    for (int k = 0; k < DV1_PROBE; ++k) {
+        ha |= (k < na) & (fabs((double)va[k] - ta.m0) <= Wa);
+        hb |= (k < nb) & (fabs((double)vb[k] - tb.m0) <= Wb);
+    }
+    ta.hit = ha;
+    tb.hit = hb;
+}
+
+__device__ __forceinline__ bool dv1_rest(const float *hu_s, const TripletProbe &t, double W, int from)
+{
+    bool hit = t.hit;
+    const int n = t.len0 + t.len1;
+    for (int k = from; k < n && !hit; ++k) {
+        const int p = k < t.len0 ? t.lo0 + k : t.lo1 + (k - t.len0);
+        hit = fabs((double)hu_s[p] - t.m0) <= W;
+    }
+    return hit;
+}
+
 __device__ __forceinline__ bool dv1_triplet(const DevGeom &G, const TrackArgs &a, const float *hu_s, const int *E,
                                    const SeedConst &sc, int k0lo, int k0hi, double W, int p3)
 {
-    const double m0 = fma((double)hu_s[p3] - sc.c[3], G.ffac[0], sc.c[0]);
-    int lo0, len0, lo1, len1;
-    sector_bins(E, a, 0, k0lo, k0hi, m0, W, lo0, len0, lo1, len1);
-    // the first two positions are read together (most probes look at <= 2 hits)
-    const int n = len0 + len1;
-    const int pa = len0 > 0 ? lo0 : lo1, pb = len0 > 1 ? lo0 + 1 : (len0 == 1 ? lo1 : lo1 + 1);
-    const float ua = hu_s[n > 0 ? pa : 0], ub = hu_s[n > 1 ? pb : 0];
-    bool hit = (n > 0 && fabs((double)ua - m0) <= W) || (n > 1 && fabs((double)ub - m0) <= W);
-    for (int k = 2; k < n && !hit; ++k) {
-        const int p = k < len0 ? lo0 + k : lo1 + (k - len0);
-        hit = fabs((double)hu_s[p] - m0) <= W;
-    }
-    return hit;
+    return dv1_rest(hu_s, dv1_probe(G, a, hu_s, E, sc, k0lo, k0hi, W, p3), W, 2);
 }
 
 // Candidate key of Dv1: the candidate index holds the UTbX hit's index in its
@@ -628,7 +682,7 @@ __device__ __forceinline__ void item_candidates_n(const DevGeom &G, const TrackA
         if (DV1) {
             int klo, khi, l1;
             sector_span(sc, L, klo, khi);
-            sector_bins(E, a, L, klo, khi, m[L], W2, lo[L], len0[L], lo1[L], l1);
+            sector_bins(E, a, G.nsec, L, klo, khi, m[L], W2, lo[L], len0[L], lo1[L], l1);
             len[L] = len0[L] + l1;
         } else {
             int hi;
@@ -642,6 +696,7 @@ __device__ __forceinline__ void item_candidates_n(const DevGeom &G, const TrackA
     // best keep (|delta|, position), u and index are re-read only on ties
     double d0[3] = {INFINITY, INFINITY, INFINITY}, d1[3] = {INFINITY, INFINITY, INFINITY};
     int p0k[3] = {-1, -1, -1}, p1k[3] = {-1, -1, -1};
+    float u0k[3] = {0.0f, 0.0f, 0.0f}, u1k[3] = {0.0f, 0.0f, 0.0f};   // their u, for the residuals
     for (int k = 0; k < maxlen; ++k) {
         // the three loads first (a finished layer re-reads its start), then the tests
         int pp[3];
@@ -664,12 +719,15 @@ __device__ __forceinline__ void item_candidates_n(const DevGeom &G, const TrackA
                 if (NL > 1) {
                     d1[L] = d0[L];
                     p1k[L] = p0k[L];
+                    u1k[L] = u0k[L];
                 }
                 d0[L] = d;
                 p0k[L] = p;
+                u0k[L] = u;
             } else if (NL > 1 && before(hu_s, hidx_s, d, u, p, d1[L], p1k[L])) {
                 d1[L] = d;
                 p1k[L] = p;
+                u1k[L] = u;
             }
         }
     }
@@ -690,11 +748,11 @@ __device__ __forceinline__ void item_candidates_n(const DevGeom &G, const TrackA
     const FitConst fc = fit_const(G, mask);
     double r0[N0], r1[N1], r2[N2];
 #pragma unroll
-    for (int i = 0; i < N0; ++i) r0[i] = A[0][i] >= 0 ? (double)hu_s[A[0][i]] - sc.c[0] : 0.0;
+    for (int i = 0; i < N0; ++i) r0[i] = A[0][i] >= 0 ? (double)(i ? u1k[0] : u0k[0]) - sc.c[0] : 0.0;
 #pragma unroll
-    for (int i = 0; i < N1; ++i) r1[i] = A[1][i] >= 0 ? (double)hu_s[A[1][i]] - sc.c[1] : 0.0;
+    for (int i = 0; i < N1; ++i) r1[i] = A[1][i] >= 0 ? (double)(i ? u1k[1] : u0k[1]) - sc.c[1] : 0.0;
 #pragma unroll
-    for (int i = 0; i < N2; ++i) r2[i] = A[2][i] >= 0 ? (double)hu_s[A[2][i]] - sc.c[2] : 0.0;
+    for (int i = 0; i < N2; ++i) r2[i] = A[2][i] >= 0 ? (double)(i ? u1k[2] : u0k[2]) - sc.c[2] : 0.0;
     const int o0 = nA[0] > 0 ? nA[0] : 1, o1 = nA[1] > 0 ? nA[1] : 1, o2 = nA[2] > 0 ? nA[2] : 1;
 #pragma unroll
     for (int i0 = 0; i0 < N0; ++i0) {
@@ -1130,6 +1188,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2
     float2 *qst = reinterpret_cast<float2 *>(it_hits + 2 * BLOCK);
     __shared__ int s_nx[8];   // next event and its offsets (fetch_event)
     __shared__ int s_bad, s_nacc, s_nitems, s_nkept;
+    __shared__ int s_long;   // Dv1: a seed of the chunk has more than 128 UTbX hits
     __shared__ int s_wsum[BLOCK / 64];
     const int tid = threadIdx.x;
 
@@ -1209,6 +1268,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2
             if (tid == 0) {
                 s_nacc = min(BLOCK, s1 - sc0);
                 s_nitems = INT_MAX;
+                s_long = 0;
             }
             // phase A: lane per seed, the UTbX bucket range of its first window;
             // every hit of the range inside the window becomes an item (seed, hit)
@@ -1256,37 +1316,68 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2
                 return DV1 ? dv1_triplet(G, a, hu_s, E, sc, k0lo, k0hi, W2, p) : fabs((double)hu_s[p] - m3) <= W1;
             };
             int n_win = 0;
+            uint32_t in_mask = 0;   // Dv0: in-window flags of the range's first 32 hits
             // Dv1 tests its axial triplets a wavefront per seed, a lane per UTbX
             // hit (tens of hits per seed): the seed constants and ranges go to LDS
             int *s_pk = reinterpret_cast<int *>(it_hits);   // free until phase B
             int *s_cnt = reinterpret_cast<int *>(s_key);    // free until the scan below
             // triplet flags of a seed's first 128 UTbX hits, kept for the write pass
             unsigned long long *s_mask = it_hits + BLOCK / 2;
-            const int lane = tid & 63, wave = tid >> 6;
+            // readfirstlane: the compiler then knows the wavefront index is uniform
+            const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
             const int n_chunk = min(BLOCK, s1 - sc0);
             if (DV1) {
                 s_c[tid] = sc;
                 s_pk[tid] = p_lo | (n_rng << 16);
                 lds_barrier();
-                for (int sl = wave; sl < n_chunk; sl += BLOCK / 64) {
-                    const int pk = s_pk[sl], plo = pk & 0xffff, nr = pk >> 16;
-                    const SeedConst scw = s_c[sl];
+                // two seeds per pass, so that their LDS round trips overlap; a lane
+                // past a seed's range probes hit 0 (in bounds) and is masked off
+                for (int sl = wave; sl < n_chunk; sl += 2 * (BLOCK / 64)) {
+                    const int sl2 = sl + BLOCK / 64;
+                    const bool two = sl2 < n_chunk;
+                    const int pk = s_pk[sl], pk2 = two ? s_pk[sl2] : 0;
+                    const int plo = pk & 0xffff, nr = pk >> 16, plo2 = pk2 & 0xffff, nr2 = pk2 >> 16;
+                    const SeedConst scw = s_c[sl], scw2 = s_c[two ? sl2 : sl];
                     const double W2w = fma(G.w2c1, fabs((double)scw.q), G.w2c0);
-                    int klo, khi;
+                    const double W2w2 = fma(G.w2c1, fabs((double)scw2.q), G.w2c0);
+                    int klo, khi, klo2, khi2;
                     sector_span(scw, 0, klo, khi);
-                    int cnt = 0;
-                    for (int k0 = 0; k0 < nr; k0 += 64) {
-                        const bool f = k0 + lane < nr && dv1_triplet(G, a, hu_s, E, scw, klo, khi, W2w, plo + k0 + lane);
-                        const unsigned long long m = __ballot(f);
-                        if (k0 < 128 && lane == 0) s_mask[2 * sl + (k0 >> 6)] = m;
+                    sector_span(scw2, 0, klo2, khi2);
+                    int cnt = 0, cnt2 = 0;
+                    for (int k0 = 0; k0 < max(nr, nr2); k0 += 64) {
+                        const int k = k0 + lane;
+                        const bool v1 = k < nr, v2 = k < nr2;
+                        TripletProbe t1, t2;
+                        dv1_probe_pair(G, a, hu_s, E, scw, scw2, klo, khi, klo2, khi2, W2w, W2w2, v1 ? plo + k : 0,
+                                       v2 ? plo2 + k : 0, t1, t2);
+                        // ballots of both first probes on every lane (nothing to sink into a
+                        // branch), the rare longer windows after them
+                        const unsigned long long h1 = __ballot(t1.hit), h2 = __ballot(t2.hit);
+                        const bool r1 = v1 && !t1.hit && dv1_rest(hu_s, t1, W2w, DV1_PROBE);
+                        const bool r2 = v2 && !t2.hit && dv1_rest(hu_s, t2, W2w2, DV1_PROBE);
+                        const unsigned long long m = (h1 & __ballot(v1)) | __ballot(r1);
+                        const unsigned long long m2 = (h2 & __ballot(v2)) | __ballot(r2);
+                        if (k0 < 128 && lane == 0) {
+                            s_mask[2 * sl + (k0 >> 6)] = m;
+                            if (two) s_mask[2 * sl2 + (k0 >> 6)] = m2;
+                        }
                         cnt += __popcll(m);
+                        cnt2 += __popcll(m2);
                     }
-                    if (lane == 0) s_cnt[sl] = cnt;
+                    if (lane == 0) {
+                        s_cnt[sl] = cnt;
+                        if (two) s_cnt[sl2] = cnt2;
+                        if (max(nr, nr2) > 128) s_long = 1;
+                    }
                 }
                 lds_barrier();
                 n_win = have ? s_cnt[tid] : 0;
             } else {
-                for (int k = 0; k < n_rng; ++k) n_win += is_item(p_lo + k) ? 1 : 0;
+                for (int k = 0; k < n_rng; ++k) {
+                    const bool in = is_item(p_lo + k);
+                    n_win += in ? 1 : 0;
+                    in_mask |= (in && k < 32) ? 1u << k : 0u;
+                }
             }
             int tot;
             const int excl = block_exclusive_scan<BLOCK>(n_win, s_wsum, &tot);
@@ -1309,29 +1400,49 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2
                 s_key[tid] = ~0ull;
                 s_base[tid] = excl;
                 if (!DV1) {
-                    for (int k = 0, w = 0; k < n_rng && w < n_win; ++k) {
-                        if (is_item(p_lo + k)) it_desc[excl + w++] = ((uint32_t)tid << 16) | (uint32_t)(p_lo + k);
+                    if (n_rng <= 32) {
+                        uint32_t m = in_mask;
+                        for (int w = 0; m != 0 && w < n_win; ++w) {
+                            const int k = __ffs(m) - 1;
+                            m &= m - 1;
+                            it_desc[excl + w] = ((uint32_t)tid << 16) | (uint32_t)(p_lo + k);
+                        }
+                    } else {
+                        for (int k = 0, w = 0; k < n_rng && w < n_win; ++k) {
+                            if (is_item(p_lo + k)) it_desc[excl + w++] = ((uint32_t)tid << 16) | (uint32_t)(p_lo + k);
+                        }
+                    }
+                } else {
+                    // Dv1, lane per seed: the triplets among the first 128 UTbX hits,
+                    // from the counting pass's flags, in hit order
+                    int w = 0;
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        unsigned long long m = 64 * j < n_rng ? s_mask[2 * tid + j] : 0ull;
+                        for (; m != 0 && w < n_win; ++w) {
+                            const int k = 64 * j + __ffsll((long long)m) - 1;
+                            m &= m - 1;
+                            it_desc[excl + w] = ((uint32_t)tid << 16) | (uint32_t)(p_lo + k);
+                        }
                     }
                 }
             }
-            if (DV1) {
-                // the triplets again, written in hit order at the seed's base
+            if (DV1 && __builtin_amdgcn_readfirstlane(s_long)) {   // uniform: written before a barrier
+                // seeds with more than 128 UTbX hits: the rest of their triplets, a
+                // wavefront per seed, after the flagged ones
                 lds_barrier();
                 const int nacc_w = s_nacc, nit_w = min(min(tot, s_nitems), a.icap);
                 for (int sl = wave; sl < nacc_w; sl += BLOCK / 64) {
                     const int pk = s_pk[sl], plo = pk & 0xffff, nr = pk >> 16;
+                    if (nr <= 128) continue;
                     const SeedConst scw = s_c[sl];
                     const double W2w = fma(G.w2c1, fabs((double)scw.q), G.w2c0);
                     int klo, khi;
                     sector_span(scw, 0, klo, khi);
                     const int base = s_base[sl], cap = (sl + 1 < nacc_w ? s_base[sl + 1] : nit_w) - base;
-                    int w = 0;
-                    for (int k0 = 0; k0 < nr && w < cap; k0 += 64) {
-                        bool f;
-                        if (k0 < 128)
-                            f = (s_mask[2 * sl + (k0 >> 6)] >> lane) & 1ull;
-                        else
-                            f = k0 + lane < nr && dv1_triplet(G, a, hu_s, E, scw, klo, khi, W2w, plo + k0 + lane);
+                    int w = __popcll(s_mask[2 * sl]) + __popcll(s_mask[2 * sl + 1]);
+                    for (int k0 = 128; k0 < nr && w < cap; k0 += 64) {
+                        const bool f = k0 + lane < nr && dv1_triplet(G, a, hu_s, E, scw, klo, khi, W2w, plo + k0 + lane);
                         const unsigned long long m = __ballot(f);
                         const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
                                                                    __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
