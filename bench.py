@@ -243,7 +243,7 @@ def main():
     traffic = stored_traffic("k_track_fused", src_hash)
     roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 5), traffic=traffic,
-                    kernel="k_track<256,false,true,false>: hit staging, search, fit, ghost-killer MLP and vertexing fused",
+                    kernel="k_track<256,false,true,false,false>: hit staging, search, fit, ghost-killer MLP and vertexing fused",
                     kernel_ms=round(fused_ms, 4), algorithmic_bytes_per_launch=round(step_bytes))
     vertex_info = dict(kept_tracks=kept, vertices=n_vtx, unfused_track_ms=round(trk_ms, 4),
                        unfused_vertex_ms=round(vtx_ms, 4), unfused_vertex_algorithmic_bytes=round(vb))

@@ -141,10 +141,14 @@ hipError_t launch_track_b(const ds::TrackArgs &a, const ds::DevGeom &G, int grid
     const ds::TrackKernArgs k{a, G};
     if (a.cmax > 0)
         hipLaunchKernelGGL((ds::k_track<B, true, false, false>), dim3(grid), dim3(B), lds, s, k);
+    else if (a.hsec && a.vcount && a.m_pipi)
+        hipLaunchKernelGGL((ds::k_track<B, false, true, true, true>), dim3(grid), dim3(B), lds, s, k);
     else if (a.hsec && a.vcount)
         hipLaunchKernelGGL((ds::k_track<B, false, true, true>), dim3(grid), dim3(B), lds, s, k);
     else if (a.hsec)
         hipLaunchKernelGGL((ds::k_track<B, false, false, true>), dim3(grid), dim3(B), lds, s, k);
+    else if (a.vcount && a.m_pipi)
+        hipLaunchKernelGGL((ds::k_track<B, false, true, false, true>), dim3(grid), dim3(B), lds, s, k);
     else if (a.vcount)
         hipLaunchKernelGGL((ds::k_track<B, false, true, false>), dim3(grid), dim3(B), lds, s, k);
     else
@@ -190,7 +194,9 @@ hipError_t set_kernel_attributes()
         reinterpret_cast<const void *>(&ds::k_track<B, true, false, false>),                                \
         reinterpret_cast<const void *>(&ds::k_track<B, false, true, false>),                                \
         reinterpret_cast<const void *>(&ds::k_track<B, false, false, true>),                                \
-        reinterpret_cast<const void *>(&ds::k_track<B, false, true, true>)
+        reinterpret_cast<const void *>(&ds::k_track<B, false, true, true>),                                 \
+        reinterpret_cast<const void *>(&ds::k_track<B, false, true, false, true>),                          \
+        reinterpret_cast<const void *>(&ds::k_track<B, false, true, true, true>)
         DS_TRACK_FNS(64), DS_TRACK_FNS(128), DS_TRACK_FNS(256), DS_TRACK_FNS(512),
 #undef DS_TRACK_FNS
         reinterpret_cast<const void *>(&ds::k_vertex<64, VTX_PPT>),

@@ -799,10 +799,17 @@ __device__ __forceinline__ int first_window_rank(const DevGeom &G, const float *
     if (!(d3 <= W1)) return -1;
     const int i3 = hidx_s[p3];
     int rank = 0;
-    for (int p = sc.lo; p < sc.hi; ++p) {
-        const float u = hu_s[p];
-        const double d = fabs((double)u - m3);
-        if (d < d3 || (d == d3 && p != p3 && key_less(d, u, (int)hidx_s[p], d3, u3, i3))) ++rank;
+    // four positions per LDS round trip
+    for (int p0 = sc.lo; p0 < sc.hi; p0 += 4) {
+        float u[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) u[j] = hu_s[p0 + j < sc.hi ? p0 + j : p3];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int p = p0 + j;
+            const double d = fabs((double)u[j] - m3);
+            if (p < sc.hi && (d < d3 || (d == d3 && p != p3 && key_less(d, u[j], (int)hidx_s[p], d3, u3, i3)))) ++rank;
+        }
     }
     return rank;
 }
@@ -1053,14 +1060,16 @@ __device__ __forceinline__ void vertex_extras(const DevGeom &G, const float *WLg
 // Vertexing of one event by the whole workgroup, from the kept tracks in LDS
 // (slot order): pairs (a < b) in row-major chunks of BLOCK, float32
 // prescreen, float64 Newton PCA of the survivors, order-preserving output.
-template <int BLOCK>
+// XTR: also the masses and trigger-line scores of each vertex (compiled only
+// where they are asked for: their registers would otherwise count against
+// every fused launch).
+template <int BLOCK, bool XTR>
 __device__ __forceinline__ void vertex_event_block(const TrackArgs &a, const DevGeom &G, int e, int s0, int n,
                                           const float4 *kst, const float *kq, const int *kslot, int *qk, int *qpass,
                                           float4 *qres, float2 *qst, int *s_wsum)
 {
     const int tid = threadIdx.x;
     const bool curved = (G.fp != 0.0);
-    const bool extras = a.m_pipi != nullptr;
     const int npairs = n * (n - 1) / 2;
     int out_n = 0;
     for (int chunk = 0; chunk < npairs; chunk += BLOCK) {
@@ -1110,7 +1119,7 @@ __device__ __forceinline__ void vertex_event_block(const TrackArgs &a, const Dev
                 a.vy[o] = R.y;
                 a.vz[o] = R.z;
                 a.vdoca[o] = R.w;
-                if (extras) {
+                if constexpr (XTR) {
                     const float4 TA = kst[ia], TB = kst[ib];
                     const double g1 = -G.fp * (G.gc0 + G.gc1 * ((double)kq[ia] * 1e-3));
                     const double g2 = -G.fp * (G.gc0 + G.gc1 * ((double)kq[ib] * 1e-3));
@@ -1155,10 +1164,12 @@ __device__ __forceinline__ void fetch_event(const TrackArgs &a, int iter, int la
     if (lane < 7 && en < a.n_events) s_nx[1 + lane] = lane < 2 ? a.seed_off[en + lane] : a.hit_off[4 * en + lane - 2];
 }
 
-template <int BLOCK, bool CANDS, bool VTX, bool DV1>
+// XTR (with VTX): the fused vertexing also writes masses and trigger-line scores.
+template <int BLOCK, bool CANDS, bool VTX, bool DV1, bool XTR = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2 : 3))) void k_track(TrackKernArgs)
 {
     static_assert(!(CANDS && DV1), "candidate rows follow Dv0");
+    static_assert(!XTR || VTX, "extras come with the fused vertexing");
     const TrackArgs &a0 = kernel_args<TrackKernArgs>().a;
     extern __shared__ __align__(16) unsigned char smem[];
     size_t off = 0;
@@ -1373,10 +1384,18 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2
                 lds_barrier();
                 n_win = have ? s_cnt[tid] : 0;
             } else {
-                for (int k = 0; k < n_rng; ++k) {
-                    const bool in = is_item(p_lo + k);
-                    n_win += in ? 1 : 0;
-                    in_mask |= (in && k < 32) ? 1u << k : 0u;
+                // four positions per LDS round trip
+                for (int k0 = 0; k0 < n_rng; k0 += 4) {
+                    float u[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) u[j] = hu_s[k0 + j < n_rng ? p_lo + k0 + j : p_lo];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int k = k0 + j;
+                        const bool in = k < n_rng && fabs((double)u[j] - m3) <= W1;
+                        n_win += in ? 1 : 0;
+                        in_mask |= (in && k < 32) ? 1u << k : 0u;
+                    }
                 }
             }
             int tot;
@@ -1571,7 +1590,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2
         }
         if (VTX) {
             const TrackKernArgs &Kv = kernel_args<TrackKernArgs>();
-            vertex_event_block<BLOCK>(Kv.a, Kv.G, e, s0, s_nkept, kst, kq, kslot, qk, qpass, qres, qst, s_wsum);
+            vertex_event_block<BLOCK, XTR>(Kv.a, Kv.G, e, s0, s_nkept, kst, kq, kslot, qk, qpass, qres, qst, s_wsum);
         }
     }
     const TrackArgs &a = kernel_args<TrackKernArgs>().a;

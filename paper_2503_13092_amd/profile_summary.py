@@ -161,15 +161,15 @@ def summarize(trace_dir, fetch_dir, write_dir, kernel_key, name, workload, algor
 
 
 def kernel_key_id(key: str) -> str:
-    return {"k_track<256, false, true, false>": "k_track_fused",
-            "k_track<256, false, true, true>": "k_track_fused_dv1"}.get(key, key)
+    return {"k_track<256, false, true, false, false>": "k_track_fused",
+            "k_track<256, false, true, true, false>": "k_track_fused_dv1"}.get(key, key)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--print-commands", action="store_true")
     ap.add_argument("--dir", default="gpurun_out")
-    ap.add_argument("--kernel", default="k_track<256, false, true, false>")
+    ap.add_argument("--kernel", default="k_track<256, false, true, false, false>")
     ap.add_argument("--name", default="k_track_fused_throughput_10k")
     ap.add_argument("--algorithmic-bytes", type=float, default=None,
                     help="per launch; default: read from the benchmark JSON line in <dir>/prof_bench.json")

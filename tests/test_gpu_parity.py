@@ -382,6 +382,44 @@ def test_every_candidate_scored_matches_oracle():
         c.close()
 
 
+@pytest.mark.parametrize("algorithm", [0, 1])
+def test_fused_step_masses_and_lines_match_standalone(algorithm):
+    """ds_process with masses and trigger-line outputs (the fused launch's
+    extras instantiation) against ds_find_tracks + ds_vertex, whose extras the
+    test above pins to the oracle."""
+    wl = synth.line_weights()
+    g = dict(G0, algorithm=algorithm)
+    b = synth.generate(0, n_events=60, seed=19)
+    c = ds.Context(0, g, W)
+    try:
+        ds.ds_load_lines(c.handle, wl)
+        outs = []
+        for fused in (False, True):
+            ev = ds.DeviceEvents(b)
+            tr = ds.DeviceTracks(b.n_seeds)
+            vt = ds.DeviceVertices(b.n_events, 256, extras=True)
+            if fused:
+                ds.ds_process(c.handle, ev, tr, vt, ds.DS_MODE_GRAPH, score_max=math.inf)
+            else:
+                ds.ds_find_tracks(c.handle, ev, tr, ds.DS_MODE_PERSISTENT, 1)
+                ds.ds_vertex(c.handle, ev, tr, math.inf, vt, ds.DS_MODE_PERSISTENT)
+            torch.cuda.synchronize()
+            outs.append(vt.to_numpy())
+        a, f = outs
+        assert a["flags"] == 0 and f["flags"] == 0
+        for k in ("count", "i", "j", "x", "y", "z", "doca"):
+            assert np.array_equal(a[k], f[k]), k
+        live = np.concatenate([np.arange(e * 256, e * 256 + int(a["count"][e])) for e in range(b.n_events)])
+        assert len(live) > b.n_events
+        for k in ("m_pipi", "m_ppi"):
+            assert np.all(np.abs(a[k][live] - f[k][live]) <= 1e-5 * np.abs(a[k][live]) + 1e-4), k
+        assert np.max(np.abs(a["lines"][live] - f["lines"][live])) <= 1e-6
+        say(f"[parity] fused extras, algorithm {algorithm}: {len(live)} vertices")
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+
+
 def test_vertex_masses_and_trigger_lines_match_oracle(ctx):
     wl = synth.line_weights()
     s = synth.vertex_track_sample(n_events=30, n_pairs=6, n_random=30, seed=41)
