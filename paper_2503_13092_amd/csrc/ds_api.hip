@@ -50,7 +50,7 @@ struct ds_ctx {
     float *d_WL = nullptr;   // trigger-line networks
     int *d_counters = nullptr;  // [MAX_STREAM_SLOTS][4]
     std::map<void *, int> slots;
-    Launch trk{256, 4, 512};
+    Launch trk{256, 3, 512};  // three resident workgroups per CU (168 VGPRs, ~50 KB LDS): one grid wave
     Launch vtx{64, 2, 0};     // measured best for the 10k-event batch (wavefront-per-event kernel)
     hipStream_t capture = nullptr;
     std::map<std::string, GraphEntry> graphs;
