@@ -64,11 +64,11 @@ ds_status dev_err(hipError_t e) { return e == hipSuccess ? DS_OK : DS_E_DEVICE; 
 
 size_t round16(size_t v) { return (v + 15) & ~size_t(15); }
 
-size_t track_lds(int hcap, int nb, int block, int icap, int tcap)
+size_t track_lds(int hcap, int nb, int nb3, int block, int icap, int tcap)
 {
     size_t off = (size_t)hcap * 4;
     off = round16(off + (size_t)hcap * 2);
-    off = round16(off + (size_t)(4 * nb + 1) * 4);
+    off = round16(off + (size_t)(3 * nb + nb3 + 1) * 4);
     off += (size_t)block * sizeof(ds::SeedConst);
     off += (size_t)block * 8;
     off = round16(off + (size_t)block * 4);
@@ -231,15 +231,19 @@ ds_status plan_track(ds_ctx *c, const ds_events *ev, const ds_tracks *out, int f
     // for sector ids out of range; candidate rows always follow Dv0
     const bool dv1 = c->algorithm == 1 && !cand_rows;
     if (dv1 && !ev->hit_sector) return DS_E_ARG;
-    const int nbu = dv1 ? std::max(4, c->trk.bins / c->G.nsec) : c->trk.bins;
-    const int nb = dv1 ? c->G.nsec * nbu + 1 : nbu;
+    // Dv1 reads layer 3 by whole sectors (one u bin each); layers 0-2 share the
+    // rest of the 4 x bins bucket budget
+    const int nsec = c->G.nsec;
+    const int nbu = dv1 ? std::max(4, (4 * c->trk.bins - nsec - 4) / (3 * nsec)) : c->trk.bins;
+    const int nb = dv1 ? nsec * nbu + 1 : nbu;
+    const int nbu3 = dv1 ? 1 : nbu, nb3 = dv1 ? nsec + 1 : nb;
     int hcap = round_up(std::max(ev->max_hits_per_event, 1), 64);
     const int block = c->trk.block;
     // items per chunk: room for ITEMS_PER_SEED per seed; a chunk shrinks when its seeds need more
     const int icap = std::max(block * ITEMS_PER_SEED, ds::MAX_L3);
     const int tcap = vertex_fused ? round_up(std::max(ev->max_seeds_per_event, 1), 64) : 0;
     if (tcap > 65535) return DS_E_CAPACITY;
-    size_t lds = track_lds(hcap, nb, block, icap, tcap);
+    size_t lds = track_lds(hcap, nb, nb3, block, icap, tcap);
     if (lds > LDS_LIMIT) return DS_E_CAPACITY;
     ds::TrackArgs &a = p->a;
     std::memset(&a, 0, sizeof(a));
@@ -281,6 +285,9 @@ ds_status plan_track(ds_ctx *c, const ds_events *ev, const ds_tracks *out, int f
     a.nbu = nbu;
     a.u0 = (float)c->u_min;
     a.inv_bw = (float)((double)nbu / (c->u_max - c->u_min));
+    a.nb3 = nb3;
+    a.nbu3 = nbu3;
+    a.inv_bw3 = (float)((double)nbu3 / (c->u_max - c->u_min));
     a.hsec = dv1 ? ev->hit_sector : nullptr;
     p->block = block;
     p->grid = std::max(1, std::min(ev->n_events, c->n_cu * c->trk.wg_per_cu));

@@ -119,9 +119,11 @@ struct TrackArgs {
     int *voverflow, *vflags;
     float *m_pipi, *m_ppi, *line0, *line1, *line2, *line3;
     const float *WL;
-    int nb;              // buckets per layer: u bins (Dv0) or sectors x u bins + 1 (Dv1)
-    int nbu;             // u bins (per sector)
+    int nb;              // buckets of layers 0-2: u bins (Dv0) or sectors x u bins + 1 (Dv1)
+    int nbu;             // u bins (per sector) of layers 0-2
     float u0, inv_bw;    // bin = floor((u - u0) * inv_bw), clamped to [0, nbu)
+    int nb3, nbu3;       // the same for layer 3 (UTbX), stored after layers 0-2; Dv1 reads it
+    float inv_bw3;       // by whole sectors only, so it has one u bin per sector
     const uint8_t *hsec; // Dv1: Y sector of every hit (null for Dv0)
 };
 
@@ -934,10 +936,12 @@ __device__ __forceinline__ void write_candidate_row(const TrackArgs &a, const De
 template <bool DV1>
 __device__ __forceinline__ int hit_bucket(const TrackArgs &a, int nsec, int L, float u, int k)
 {
-    int b = L * a.nb + bin_of(u, a.u0, a.inv_bw, a.nbu);
+    const bool l3 = DV1 && L == 3;   // Dv0's layer 3 has the common layout
+    const int nbu = l3 ? a.nbu3 : a.nbu;
+    int b = L * a.nb + bin_of(u, a.u0, l3 ? a.inv_bw3 : a.inv_bw, nbu);
     if (DV1) {
         const int sec = a.hsec[k];
-        b = sec < nsec ? b + sec * a.nbu : L * a.nb + nsec * a.nbu;
+        b = sec < nsec ? b + sec * nbu : L * a.nb + nsec * nbu;
     }
     return b;
 }
@@ -948,7 +952,7 @@ constexpr int STAGE_HPT = 16;   // hits per lane per staging round
 // layer's hits into the layer's buckets, scans them (64 buckets per step, DPP
 // sums) and places the hits, with no workgroup barrier until the end: a
 // wavefront's LDS operations complete in order.  Same result as a workgroup
-// counting sort: E[b] = start of bucket b, E[4*nb] = count.  *s_bad must be 0
+// counting sort: E[b] = start of bucket b, E[3*nb + nb3] = count.  *s_bad must be 0
 // on entry.
 template <int BLOCK, bool DV1, typename Between>
 __device__ __forceinline__ bool stage_hits_w(const TrackArgs &a, int nsec, int hb, const int hl[4], int nh,
@@ -956,8 +960,8 @@ __device__ __forceinline__ bool stage_hits_w(const TrackArgs &a, int nsec, int h
 {
     constexpr int HPT = STAGE_HPT;
     constexpr int NW = BLOCK / 64;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int nb = a.nb;
+    // readfirstlane: the layer index is then known to be wavefront-uniform
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     // the first layer's loads are in flight while `between` runs
     int L = wave;
     int lo = L < 4 ? hl[L] : 0, n = L < 4 ? (L < 3 ? hl[L + 1] : nh) - hl[L] : 0;
@@ -980,7 +984,8 @@ __device__ __forceinline__ bool stage_hits_w(const TrackArgs &a, int nsec, int h
                 u[j] = (k < n) ? a.hu[hb + lo + k] : 0.0f;
             }
         }
-        int *EL = E + 1 + L * nb;   // EL[b]: count, then end, of bucket (L, b)
+        int *EL = E + 1 + L * a.nb;   // EL[b]: count, then end, of bucket (L, b)
+        const int nb = (DV1 && L == 3) ? a.nb3 : a.nb;
         for (int b = lane; b < nb; b += 64) EL[b] = 0;
         const int rounds = (n + 64 * HPT - 1) / (64 * HPT);
         for (int r = 0; r < rounds; ++r) {
@@ -1178,7 +1183,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2
     uint16_t *hidx_s = reinterpret_cast<uint16_t *>(smem + off);
     off = (off + (size_t)a0.hcap * 2 + 15) & ~(size_t)15;
     int *E = reinterpret_cast<int *>(smem + off);
-    off = (off + (size_t)(4 * a0.nb + 1) * 4 + 15) & ~(size_t)15;
+    off = (off + (size_t)(3 * a0.nb + a0.nb3 + 1) * 4 + 15) & ~(size_t)15;
     SeedConst *s_c = reinterpret_cast<SeedConst *>(smem + off);
     off += (size_t)BLOCK * sizeof(SeedConst);
     unsigned long long *s_key = reinterpret_cast<unsigned long long *>(smem + off);
@@ -1306,8 +1311,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2
                         int klo, khi;
                         sector_span(sc, 3, klo, khi);
                         if (klo <= khi) {
-                            p_lo = E[3 * a.nb + klo * a.nbu];
-                            p_hi = E[3 * a.nb + (khi + 1) * a.nbu];
+                            p_lo = E[3 * a.nb + klo * a.nbu3];
+                            p_hi = E[3 * a.nb + (khi + 1) * a.nbu3];
                         }
                     } else if (G.max_l3 > 0) {
                         bin_range(E, 3, a.nb, a.u0, a.inv_bw, m3, W1, p_lo, p_hi);
