@@ -32,17 +32,17 @@ SQ_SETS = (
 SQ_BENCH = "python $REPO/bench.py --steps 3 --warmup 1 --no-plain --no-cpu-baseline --no-serve --no-copy-ceiling"
 
 
-def sq_commands(out_dir: str = "gpurun_out"):
-    return [f"rocprofv3 --pmc {c} --output-format csv -d $REPO/{out_dir}/pmc_sq{k} -o sq -- {SQ_BENCH}"
+def sq_commands():
+    return [f"rocprofv3 --pmc {c} --output-format csv -d $OUT/pmc_sq{k} -o sq -- {SQ_BENCH}"
             for k, c in enumerate(SQ_SETS)]
 
 
-def commands(out_dir: str = "gpurun_out", steps: int = 10, config: int = 1):
-    """The three profiler runs, each started in /tmp with TMPDIR=/tmp and
-    $REPO set to the repository root; the trace run's stdout (the benchmark's
-    JSON line) goes to <out_dir>/prof_bench.json."""
+def commands(steps: int = 10, config: int = 1):
+    """The three profiler runs, each started in /tmp with TMPDIR=/tmp, $REPO
+    set to the repository root and $OUT to the output directory; the trace
+    run's stdout (the benchmark's JSON line) goes to $OUT/prof_bench.json."""
     bench = BENCH.format(steps=steps) + ("" if config == 1 else f" --config {config}")
-    d = f"$REPO/{out_dir}"
+    d = "$OUT"
     return {
         "trace": f"rocprofv3 --kernel-trace --stats --output-format csv -d {d}/prof_trace -o trace -- {bench}"
                  f" > {d}/prof_bench.json",
@@ -101,7 +101,8 @@ def summarize(trace_dir, fetch_dir, write_dir, kernel_key, name, workload, algor
 
     lines = [f"# {name}", "",
              f"Workload: {workload}.  Kernel source hash {src}.", "",
-             "Commands (each in /tmp with `TMPDIR=/tmp`, `$REPO` = repository root):", ""]
+             "Commands (each in /tmp with `TMPDIR=/tmp`, `$REPO` = repository root, `$OUT` = output "
+             "directory):", ""]
     lines += [f"    {c}" for c in cmds.values()]
     lines += ["", "## Kernel time (rocprofv3 --kernel-trace --stats)", "",
               "| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
@@ -168,7 +169,7 @@ def kernel_key_id(key: str) -> str:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--print-commands", action="store_true")
-    ap.add_argument("--dir", default="gpurun_out")
+    ap.add_argument("--dir", default="prof_out", help="output directory of the profiler runs ($OUT)")
     ap.add_argument("--kernel", default="k_track<256, false, true, false, false>")
     ap.add_argument("--name", default="k_track_fused_throughput_10k")
     ap.add_argument("--algorithmic-bytes", type=float, default=None,
@@ -177,7 +178,7 @@ def main():
     ap.add_argument("--config", type=int, default=1)
     args = ap.parse_args()
     if args.print_commands:
-        for k, c in commands(args.dir, args.steps, args.config).items():
+        for k, c in commands(args.steps, args.config).items():
             print(f"{k}\t{c}")
         return
     ab = args.algorithmic_bytes
