@@ -383,6 +383,36 @@ def test_every_candidate_scored_matches_oracle():
 
 
 @pytest.mark.parametrize("algorithm", [0, 1])
+def test_launch_shapes_bitwise_equal(algorithm):
+    """Block size, workgroups per CU and hit bins (the autotuner's knobs)
+    change chunking, scheduling and the bucket layout, never the results."""
+    g = dict(G0, algorithm=algorithm)
+    b = synth.generate(0, n_events=80, seed=23)
+    c = ds.Context(0, g, W)
+    try:
+        outs = []
+        for block, wpc, bins in ((256, 3, 512), (64, 8, 512), (128, 4, 256), (512, 1, 1024), (256, 2, 128)):
+            say(f"[parity] launch shape, algorithm {algorithm}: block {block}, {wpc} per CU, {bins} bins")
+            ds.ds_set_launch(c.handle, 0, block, wpc, bins)
+            ev = ds.DeviceEvents(b)
+            tr = ds.DeviceTracks(b.n_seeds)
+            vt = ds.DeviceVertices(b.n_events, 256)
+            ds.ds_process(c.handle, ev, tr, vt, ds.DS_MODE_GRAPH, score_max=math.inf)
+            torch.cuda.synchronize()
+            outs.append((tr.to_numpy(), vt.to_numpy()))
+        t0, v0 = outs[0]
+        assert (t0["nhits"] > 0).sum() > 500 and t0["flags"] == 0
+        for t, v in outs[1:]:
+            for k in ("x", "y", "tx", "ty", "qop", "chi2", "score", "hits", "nhits"):
+                assert np.array_equal(t[k], t0[k]), k
+            for k in ("count", "i", "j", "x", "y", "z", "doca"):
+                assert np.array_equal(v[k], v0[k]), k
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+
+
+@pytest.mark.parametrize("algorithm", [0, 1])
 def test_fused_step_masses_and_lines_match_standalone(algorithm):
     """ds_process with masses and trigger-line outputs (the fused launch's
     extras instantiation) against ds_find_tracks + ds_vertex, whose extras the
