@@ -222,7 +222,9 @@ void ds_destroy(ds_ctx *ctx);
  * HOST array of n_weights = 1121 floats: W1[32][17], b1[32], W2[16][32],
  * b2[16], W3[1][16], b3[1] (row-major; the network of "Ghost-Killer Neural
  * Network" widened to 17 -> 32 -> 16 -> 1, ReLU hidden layers, sigmoid
- * output).  Copied to device memory, which stays resident.  Synchronous.
+ * output).  Copied to device memory, which stays resident.  Synchronous:
+ * first waits for all work on the context's device (launches already
+ * enqueued keep the old geometry and weights), then replaces both.
  */
 ds_status ds_load_geometry(ds_ctx *ctx, const ds_geometry *g, const float *mlp_weights, size_t n_weights);
 
@@ -262,8 +264,12 @@ int ds_candidate_slots(ds_ctx *ctx);
 /* Score every valid candidate of every seed (see ds_candidates). */
 ds_status ds_score_candidates(ds_ctx *ctx, const ds_events *ev, const ds_candidates *out, void *hip_stream);
 
-/* Ghost-killer scores of the tracks in `trk` (reads the stored track, the
- * seed and the chosen hits; writes trk->score). */
+/* Ghost-killer scores of the tracks in `trk` ("Ghost-Killer Neural Network":
+ * a small fully connected network scores each reconstructed track; "Ghost
+ * Rejection": tracks scoring at or above the threshold are dropped
+ * downstream).  Reads the stored track, the seed and the chosen hits; writes
+ * trk->score (0 for seeds without a track).  Device-side offset errors and
+ * hit indices outside their run set DS_F_BAD_OFFSETS in trk->flags. */
 ds_status ds_ghost_kill(ds_ctx *ctx, const ds_events *ev, const ds_tracks *trk, void *hip_stream);
 
 /*

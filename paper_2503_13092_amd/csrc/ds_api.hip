@@ -32,8 +32,22 @@ struct Launch {
 struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;   // recorded after every replay: the graph is idle once it has completed
     uint64_t last_use = 0;
 };
+
+// Destroy a cached graph once its last replay has finished (a replay may
+// still be running on a caller stream).
+void release_graph(GraphEntry &g)
+{
+    if (g.done) {
+        (void)hipEventSynchronize(g.done);
+        (void)hipEventDestroy(g.done);
+    }
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g = GraphEntry{};
+}
 
 }  // namespace
 
@@ -458,8 +472,7 @@ ds_status run_maybe_graph(ds_ctx *c, int mode, const std::string &key, hipStream
             auto victim = c->graphs.begin();
             for (auto g = c->graphs.begin(); g != c->graphs.end(); ++g)
                 if (g->second.last_use < victim->second.last_use) victim = g;
-            (void)hipGraphExecDestroy(victim->second.exec);
-            (void)hipGraphDestroy(victim->second.graph);
+            release_graph(victim->second);
             c->graphs.erase(victim);
         }
         GraphEntry ge;
@@ -472,14 +485,17 @@ ds_status run_maybe_graph(ds_ctx *c, int mode, const std::string &key, hipStream
             return DS_E_DEVICE;
         }
         err = hipGraphInstantiate(&ge.exec, ge.graph, nullptr, nullptr, 0);
+        if (err == hipSuccess) err = hipEventCreateWithFlags(&ge.done, hipEventDisableTiming);
         if (err != hipSuccess) {
-            (void)hipGraphDestroy(ge.graph);
+            release_graph(ge);
             return DS_E_DEVICE;
         }
         it = c->graphs.emplace(key, ge).first;
     }
     it->second.last_use = ++c->tick;
-    return dev_err(hipGraphLaunch(it->second.exec, s));
+    hipError_t err = hipGraphLaunch(it->second.exec, s);
+    if (err == hipSuccess) err = hipEventRecord(it->second.done, s);
+    return dev_err(err);
 }
 
 std::string graph_key(int kind, const void *args, size_t n, int block, int grid, size_t lds)
@@ -542,10 +558,7 @@ void ds_destroy(ds_ctx *c)
 {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    for (auto &g : c->graphs) {
-        (void)hipGraphExecDestroy(g.second.exec);
-        (void)hipGraphDestroy(g.second.graph);
-    }
+    for (auto &g : c->graphs) release_graph(g.second);
     if (c->d_W) (void)hipFree(c->d_W);
     if (c->d_WL) (void)hipFree(c->d_WL);
     if (c->d_counters) (void)hipFree(c->d_counters);
@@ -571,6 +584,9 @@ ds_status ds_load_geometry(ds_ctx *c, const ds_geometry *g, const float *w, size
         return DS_E_ARG;
     std::lock_guard<std::mutex> lock(c->mu);
     if (hipSetDevice(c->device) != hipSuccess) return DS_E_DEVICE;
+    // launches already enqueued on any stream read the resident weights and
+    // the cached graphs: let them finish before either is replaced
+    if (hipDeviceSynchronize() != hipSuccess) return DS_E_DEVICE;
     ds::DevGeom G{};
     for (int L = 0; L < 4; ++L) {
         G.zl[L] = g->z_layer[L];
@@ -634,10 +650,7 @@ ds_status ds_load_geometry(ds_ctx *c, const ds_geometry *g, const float *w, size
     c->clone_kill = g->clone_kill != 0;
     c->algorithm = g->algorithm;
     // cached graphs hold the old geometry as kernel arguments
-    for (auto &e : c->graphs) {
-        (void)hipGraphExecDestroy(e.second.exec);
-        (void)hipGraphDestroy(e.second.graph);
-    }
+    for (auto &e : c->graphs) release_graph(e.second);
     c->graphs.clear();
     c->loaded = true;
     return DS_OK;

@@ -177,6 +177,10 @@ class ServeStats:
     mean_batch: float
     max_in_flight: int
     rejected: int = 0
+    offered: int = 0       # arrivals scheduled before the loop ended
+    completed: int = 0     # events whose results came back (rejected ones excluded)
+    censored: int = 0      # offered, admitted or queued, not finished when the loop ended
+    saturated: bool = False  # censored > 0: the percentiles are lower bounds
 
     def as_dict(self):
         return dataclasses.asdict(self)
@@ -211,11 +215,13 @@ class Server:
         """Serve arrivals (seconds from start).  Returns (latencies_s, stats)."""
         N = len(arrivals)
         lat = np.full(N, np.nan)
+        is_rej = np.zeros(N, bool)
         free = list(range(self.be.n_slots))
         busy = {}
         head = 0           # first event not yet submitted
         arrived = 0
-        done_n = 0
+        done_n = 0         # finished or rejected: the loop ends when every arrival is one of them
+        completed = 0
         batches = []
         max_if = 0
         rejected = 0
@@ -233,6 +239,7 @@ class Server:
                     res = self.be.fetch(slot)
                     lat[a0:a1] = t - arrivals[a0:a1]
                     done_n += a1 - a0
+                    completed += a1 - a0
                     free.append(slot)
                     if on_result is not None:
                         on_result(a0, a1, res)
@@ -241,6 +248,7 @@ class Server:
                 if e1 == head:
                     # larger than a slot: rejected at admission
                     rejected += 1
+                    is_rej[head] = True
                     done_n += 1
                     head += 1
                     continue
@@ -257,14 +265,21 @@ class Server:
                 if dt > 2e-4:
                     time.sleep(dt - 1e-4)
         dur = time.perf_counter() - t0
+        # events offered before the end but not finished: their latency is at
+        # least (end - arrival); counted that way, so a saturated server's
+        # percentiles are lower bounds rather than taken over the survivors
+        offered = arrivals <= dur
+        unfinished = offered & ~np.isfinite(lat) & ~is_rej
+        L_all = np.where(unfinished, dur - arrivals, lat)
         k0 = int(warmup_frac * N)
-        L = lat[k0:]
-        L = L[np.isfinite(L)]
+        sel = offered[k0:] & ~is_rej[k0:]
+        L = L_all[k0:][sel]
         rate = N / arrivals[-1] if N else 0.0
-        stats = ServeStats(rate=rate, n=len(L), duration_s=dur, sustained=done_n / dur if dur > 0 else 0.0,
+        stats = ServeStats(rate=rate, n=len(L), duration_s=dur, sustained=completed / dur if dur > 0 else 0.0,
                            p50_ms=float(np.percentile(L, 50) * 1e3) if len(L) else math.nan,
                            p99_ms=float(np.percentile(L, 99) * 1e3) if len(L) else math.nan,
                            p999_ms=float(np.percentile(L, 99.9) * 1e3) if len(L) else math.nan,
                            mean_batch=float(np.mean(batches)) if batches else 0.0, max_in_flight=max_if,
-                           rejected=rejected)
+                           rejected=rejected, offered=int(offered.sum()), completed=completed,
+                           censored=int(unfinished.sum()), saturated=bool(unfinished.any()))
         return lat, stats

@@ -73,7 +73,7 @@ def test_dv1_config0(ctx):
     assert (ref["tracks"]["nhits"] > 0).sum() > 500
 
 
-@pytest.mark.parametrize("config,n", [(1, 40), (2, 120), (4, 10)])
+@pytest.mark.parametrize("config,n", [(1, 40), (2, 120), (4, 10), (5, 4)])
 def test_dv1_config_subsets(ctx, config, n):
     b = synth.generate(config, n_events=n, seed=31 + config)
     check(ctx.handle, b, f"config{config}")

@@ -310,6 +310,102 @@ def test_full_throughput_batch_sampled(ctx):
     say(f"[parity] full config1 sample: identical {tc['identical']}/{tc['n']}")
 
 
+@pytest.mark.parametrize("config,n,cap", [(4, 40, 1024), (2, 300, 1024), (1, 400, 1024), (4, 12, 16)])
+def test_fused_process_graph_matches_oracle(ctx, config, n, cap):
+    """The benchmark's launch (ds_process: one fused persistent launch of
+    tracking, ghost-killer and vertexing, replayed from a hipGraph) against the
+    oracle with every found track vertexed (score_max = inf): thousands of
+    pairs per event at the stress occupancy, uneven events, and a cap of 16
+    vertices per event so that the overflow count is exercised."""
+    b = synth.generate(config, n_events=n, seed=50 + config)
+    say(f"[parity] fused process config{config}x{n} cap {cap}: {b.n_seeds} seeds, {b.n_hits} hits")
+    ev = ds.DeviceEvents(b)
+    tr = ds.DeviceTracks(b.n_seeds)
+    vt = ds.DeviceVertices(b.n_events, cap)
+    ds.ds_process(ctx.handle, ev, tr, vt, ds.DS_MODE_GRAPH, score_max=math.inf)
+    torch.cuda.synchronize()
+    gt, gv = tr.to_numpy(), vt.to_numpy()
+    assert gt["flags"] == 0 and gv["flags"] == 0
+    ref = O.run_path(b, G0, W, score_max=math.inf, cap=cap, n_threads=8)
+    tc = parity.compare_tracks(gt, ref["tracks"])
+    found = ref["tracks"]["nhits"] > 0
+    sc = parity.compare_scores(gt["score"], ref["score"], found & (gt["nhits"] == ref["tracks"]["nhits"]))
+    vc = parity.compare_vertices(gv, ref["vertices"], G0["doca_max"], parity.excused_slot_set(b, tc, sc))
+    if not (vc["only_gpu"] or vc["only_ref"]):
+        assert np.array_equal(gv["count"], ref["vertices"]["count"])
+        assert gv["overflow"] == ref["vertices"]["overflow"]
+    if cap < 64:
+        assert ref["vertices"]["overflow"] > 0
+    say(f"[parity] fused process config{config}x{n}: identical {tc['identical']}/{tc['n']}, vertices "
+        f"{vc['n_gpu']}/{vc['n_ref']}, overflow {gv['overflow']}/{ref['vertices']['overflow']}")
+    assert vc["n_ref"] > (1000 if config == 4 else 0)
+
+
+def _edge_event(rng, g, xs_ut, n_noise=40):
+    """One hand-built event whose true tracks cross the UT near and beyond the
+    hit-binning range |u| <= u_max: hits are forward-simulated from states
+    before the kink (u = x - y tan(alpha) at each layer, 0.05 mm smear),
+    seeds are the kinked lines at z_seed, and noise hits crowd the same
+    u region on both sides of the range."""
+    zl, tana, zr = np.asarray(g["z_layer"]), np.asarray(g["tan_stereo"]), g["z_ref"]
+    hits = [[], [], [], []]
+    secs = [[], [], [], []]
+    seeds = []
+    for k, x0 in enumerate(xs_ut):
+        y0 = (300.0 if k % 2 else -250.0) + rng.uniform(-50, 50)
+        txb, ty = x0 / 2500.0 + rng.normal(0, 0.01), y0 / 2500.0
+        qop = (1.0 if k % 2 else -1.0) / rng.uniform(2.0, 20.0)
+        for L in range(4):
+            x = x0 + txb * (zl[L] - zr)
+            y = y0 + ty * (zl[L] - zr)
+            hits[L].append(x - y * tana[L] + rng.normal(0, g["sigma_hit"]))
+            secs[L].append(int(synth.sector_of(y, g)))
+        xm = x0 + txb * (g["z_magnet"] - zr)
+        txa = txb + g["polarity"] * g["kick"] * qop
+        seeds.append((xm + txa * (g["z_seed"] - g["z_magnet"]), y0 + ty * (g["z_seed"] - zr), txa, ty, qop))
+    for L in range(4):
+        for side in (1.0, -1.0):
+            u = side * rng.uniform(g["u_max"] - 15.0, g["u_max"] + 60.0, n_noise)
+            y = rng.uniform(-700, 700, n_noise)
+            hits[L].extend(u.tolist())
+            secs[L].extend(synth.sector_of(y, g).tolist())
+    order = [rng.permutation(len(h)) for h in hits]
+    return dict(seeds=seeds, hits=[[hits[L][i] for i in order[L]] for L in range(4)],
+                sectors=[[secs[L][i] for i in order[L]] for L in range(4)])
+
+
+@pytest.mark.parametrize("algorithm", [0, 1])
+def test_hits_beyond_binning_range(algorithm):
+    """Hits with u outside [u_min, u_max] land in the edge bins of the window
+    lookup; windows that reach past the range must still select exactly what
+    the oracle (full scans, no binning) selects."""
+    g = dict(G0, algorithm=algorithm)
+    rng = np.random.default_rng(23)
+    evs = [_edge_event(rng, g, [855.0, 870.0, 905.0, -858.0, -880.0, -920.0]) for _ in range(6)]
+    b = synth.batch_from_lists(evs)
+    c = ds.Context(0, g, W)
+    try:
+        say(f"[parity] beyond binning range, algorithm {algorithm}: {b.n_seeds} seeds, {b.n_hits} hits")
+        gt, gv = gpu_run(c.handle, b, g=g, score_max=math.inf)
+        ref = O.run_path(b, g, W, score_max=math.inf, cap=1024)
+        tc = parity.compare_tracks(gt, ref["tracks"])
+        assert gt["flags"] == 0
+        rt = ref["tracks"]
+        assert (rt["nhits"] == 4).sum() >= 30
+        outside = 0
+        for e in range(b.n_events):
+            for i in range(b.seed_off[e], b.seed_off[e + 1]):
+                for L in range(4):
+                    h = rt["hits"][i, L]
+                    if h >= 0 and abs(b.hu[b.hit_off[4 * e + L] + h]) > g["u_max"]:
+                        outside += 1
+        assert outside >= 50, outside
+        say(f"[parity] beyond binning range, algorithm {algorithm}: identical {tc['identical']}/{tc['n']}, "
+            f"{outside} selected hits outside the range")
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+
 def test_clone_killing_matches_oracle():
     g = dict(G0, clone_kill=1)
     c = ds.Context(0, g, W)

@@ -366,6 +366,48 @@ def _track_through(point, tx, ty, zr):
     return [point[0] + tx * (zr - point[2]), point[1] + ty * (zr - point[2]), tx, ty, 0.1]
 
 
+def test_features_hand_computed_all_seventeen():
+    """Every input of the ghost-killer on a track with known, non-zero
+    residuals in all four layers, against values worked out by hand from the
+    feature table (scales 1/1000, 1/0.3, 1/0.5, 1/10, (n - 3.5)/0.5, 1/3000,
+    residual hit - track over 5 sigma, magnet-plane mismatch track - seed in
+    mm).  A wrong scale, sign or layer index changes at least one entry."""
+    g = G
+    # stored track at z_ref = 2484.5: x, y, tx, ty, q/p, chi2
+    trk = [100.0, -200.0, 0.03, -0.06, 0.25, 7.5]
+    seed = [1500.0, -900.0, 0.15, -0.1, -0.4]
+    # layer offsets dz = z_L - z_ref: -157.5, -112.5, 112.5, 157.5
+    # track x at the layers: 95.275, 96.625, 103.375, 104.725
+    # track y at the layers: -190.55, -193.25, -206.75, -209.45
+    # hits put 0.25, -0.5, 0.125, 1.0 mm from the track (hit - track, in x)
+    t5 = math.tan(math.radians(5.0))
+    hit_u = [95.275 + 0.25,
+             96.625 - 0.5 + 193.25 * t5,      # u = x - y tan(+5 deg)
+             103.375 + 0.125 - 206.75 * t5,   # u = x - y tan(-5 deg)
+             104.725 + 1.0]
+    f = O.features(g, trk, 4, seed, hit_u)
+    expect = [
+        0.1, -0.2,           # x, y / 1000
+        0.1, -0.2,           # tx, ty / 0.3
+        0.5,                 # q/p / 0.5
+        0.75,                # chi2 / 10
+        1.0,                 # (4 - 3.5) / 0.5
+        0.5, -0.3,           # seed x, y / 3000
+        0.3, -0.2,           # seed tx, ty / 0.5
+        -0.8,                # seed q/p / 0.5
+        1.0, -2.0, 0.5, 4.0,  # residual / (5 * 0.05 mm)
+        # (100 + 0.03 * (5280 - 2484.5)) - (1500 + 0.15 * (5280 - 7826))
+        #   = 183.865 - 1118.1
+        -934.235,
+    ]
+    assert np.allclose(f, expect, rtol=0, atol=1e-9), np.c_[f, expect]
+    # the same track without its UTaU hit: n = 3 and that residual is 0
+    f3 = O.features(g, trk, 3, seed, [hit_u[0], np.nan, hit_u[2], hit_u[3]])
+    e3 = list(expect)
+    e3[6], e3[13] = -1.0, 0.0
+    assert np.allclose(f3, e3, rtol=0, atol=1e-9), np.c_[f3, e3]
+
+
 def test_pca_constructed_skew_lines():
     g = geom(fringe_polarity=0.0)
     rng = np.random.default_rng(8)
@@ -613,3 +655,58 @@ def test_trigger_line_network_inputs_and_structure():
         wl[l * nw + nw - 1] = l - 1.5
     out = O.vertex_extras(g, t1, t2, q1, q2, 1500.0, 1500.0, V, wl)
     assert np.allclose(out[2:], [1.0 / (1.0 + math.exp(-(l - 1.5))) for l in range(4)], atol=1e-15)
+
+
+def _one_hot_lines(k, sign):
+    """Four line networks that return sigmoid(relu(sign * input k))."""
+    nw = 32 * 12 + 32 + 32 + 1
+    wl = np.zeros(4 * nw)
+    for l in range(4):
+        wl[l * nw + k] = sign                  # W1[0][k]
+        wl[l * nw + 32 * 12 + 32] = 1.0        # W2[0][0]
+    return wl
+
+
+def test_trigger_line_inputs_second_track_masses_and_pt():
+    """Inputs 4 and 5 (second track's slopes / 0.3), 9 and 10 (mass offsets
+    from 497.6 and 1115.7 MeV, / 100) and 11 (pair transverse momentum, GeV)
+    read back through sign-aware one-hot networks, with hand-derived values:
+    constructed two-body decays fix the masses exactly, and the pair's
+    transverse momentum is the parent's, P * |(dx, dy)| / |(dx, dy, 1)|."""
+    g = geom(fringe_polarity=0.0)
+    sig = lambda v: 1.0 / (1.0 + math.exp(-v))
+    V = [30.0, 40.0, 1500.0, 0.25]
+    t1 = [1.0, 2.0, 0.1, 0.05, 0.0]
+    t2 = [3.0, 1.0, -0.06, 0.03, 0.0]
+    for k, val in ((4, -0.06 / 0.3), (5, 0.03 / 0.3)):
+        out = O.vertex_extras(g, t1, t2, 0.08, -1.0 / 3.0, 1500.0, 1500.0, V, _one_hot_lines(k, np.sign(val)))
+        assert np.allclose(out[2:], sig(abs(val)), rtol=0, atol=1e-12), k
+    zr = g["z_ref"]
+    rng = np.random.default_rng(11)
+    cases = (
+        # K0S -> pi+ pi-: input 9 = (497.611 - 497.6) / 100
+        (0.497611, 0.13957039, 0.13957039, 9, (497.611 - 497.6) / 100.0),
+        # Lambda -> p pi- (faster track = proton): input 10 = (1115.683 - 1115.7) / 100
+        (1.115683, 0.93827209, 0.13957039, 10, (1115.683 - 1115.7) / 100.0),
+    )
+    n = 0
+    for M, m1, m2, k, val in cases:
+        while True:
+            P, axis = 20.0, (0.08, -0.06)
+            p1, p2 = _two_body(M, m1, m2, P, rng.uniform(0.3, 2.8), rng.uniform(0, 6.28), axis)
+            if k == 9 or np.linalg.norm(p1) > np.linalg.norm(p2):
+                break
+        Vz = 800.0
+        trs = []
+        for p in (p1, p2):
+            tx, ty = p[0] / p[2], p[1] / p[2]
+            trs.append([tx * (zr - Vz), ty * (zr - Vz), tx, ty, 0.0])
+        args = (g, trs[0], trs[1], 1.0 / np.linalg.norm(p1), -1.0 / np.linalg.norm(p2), Vz, Vz, [0.0, 0.0, Vz, 0.0])
+        out = O.vertex_extras(*args, _one_hot_lines(k, np.sign(val)))
+        assert np.allclose(out[2:], sig(abs(val)), rtol=0, atol=1e-8), (k, out[2:], sig(abs(val)))
+        # pair pT = 20 GeV * 0.1 / sqrt(1.01): |(0.08, -0.06)| = 0.1
+        pt = 20.0 * 0.1 / math.sqrt(1.01)
+        out = O.vertex_extras(*args, _one_hot_lines(11, 1.0))
+        assert np.allclose(out[2:], sig(pt), rtol=0, atol=1e-9), (out[2:], sig(pt))
+        n += 1
+    assert n == 2

@@ -115,3 +115,30 @@ def test_latency_is_from_scheduled_arrival(pool):
     lat, st = srv.run(arr, warmup_frac=0.0)
     # at least the service time; well under the 20 ms spacing (host scheduling noise allowed)
     assert np.all(lat >= 5e-3) and np.median(lat) < 5e-3 + 12e-3
+
+
+def test_saturated_server_reports_censored_lower_bounds(pool):
+    """A server slower than the arrivals, stopped by its time limit: events
+    still queued count with (end - arrival) as a lower bound on their latency,
+    'sustained' counts completed events only, and the run says it is censored."""
+    be = FakeBackend(pool, n_slots=1, max_events=2, service=lambda n: 20e-3)
+    srv = serve.Server(be, pool)
+    arr = serve.poisson_arrivals(2000.0, 400, seed=6)
+    lat, st = srv.run(arr, warmup_frac=0.0, time_limit_s=0.15)
+    assert st.saturated and st.censored > 0
+    assert st.completed == int(np.sum(np.isfinite(lat)))
+    assert st.completed + st.censored + st.rejected == st.offered
+    assert st.sustained == pytest.approx(st.completed / st.duration_s)
+    # the median over all offered events is at least what the queue already waited
+    waited = np.sort(st.duration_s - arr[(arr <= st.duration_s) & ~np.isfinite(lat)])
+    assert st.p50_ms >= 1e3 * np.median(np.concatenate([waited, lat[np.isfinite(lat)]])) - 1e-6
+
+
+def test_rejected_events_are_not_counted_as_served(pool):
+    cap_seeds = int(pool.seeds_per_event[:10].max()) + 1
+    be = FakeBackend(pool, max_seeds=cap_seeds)
+    srv = serve.Server(be, pool)
+    lat, st = srv.run(serve.poisson_arrivals(2000.0, 40, seed=4))
+    assert st.rejected > 0 and not st.saturated
+    assert st.completed == 40 - st.rejected
+    assert st.sustained == pytest.approx(st.completed / st.duration_s)
