@@ -298,6 +298,24 @@ ds_status ds_set_launch(ds_ctx *ctx, int kernel, int block, int wg_per_cu, int b
 /* Current launch settings of `kernel` (same meaning as ds_set_launch). */
 ds_status ds_get_launch(ds_ctx *ctx, int kernel, int *block, int *wg_per_cu, int *bins);
 
+/* Event order of the persistent tracking launch. */
+enum {
+    DS_ORDER_INPUT = 0,        /* events taken from the work counter in batch order */
+    DS_ORDER_LARGEST_FIRST = 1 /* largest first (seeds + hits/8), so that uneven batches do not end on
+                                  one large event ("GPU Implementation": events of a slice differ in size) */
+};
+
+/*
+ * Set / read the event order of ds_find_tracks and ds_process in
+ * DS_MODE_PERSISTENT and DS_MODE_GRAPH (per-event launches ignore it).
+ * Largest-first adds two small launches that sort the batch's events by a
+ * work estimate into a per-stream workspace the library allocates (and grows,
+ * after draining the device, when a larger batch comes).  Results do not
+ * depend on the order; only speed does.
+ */
+ds_status ds_set_event_order(ds_ctx *ctx, int order);
+ds_status ds_get_event_order(ds_ctx *ctx, int *order);
+
 /* Human-readable name of a status code (static string). */
 const char *ds_status_str(ds_status s);
 

@@ -29,6 +29,13 @@ struct Launch {
     int block, wg_per_cu, bins;
 };
 
+// Largest-first event order of one stream slot: ORDER_WS ints of bin counts
+// and cursors (zero between calls), then the order of up to `cap` events.
+struct OrderWs {
+    int *p = nullptr;
+    int cap = 0;
+};
+
 struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -64,6 +71,8 @@ struct ds_ctx {
     float *d_WL = nullptr;   // trigger-line networks
     int *d_counters = nullptr;  // [MAX_STREAM_SLOTS][4]
     std::map<void *, int> slots;
+    OrderWs order_ws[MAX_STREAM_SLOTS];
+    int event_order = DS_ORDER_INPUT;   // persistent launches: DS_ORDER_*
     Launch trk{256, 3, 512};  // three resident workgroups per CU (168 VGPRs, ~50 KB LDS): one grid wave
     Launch vtx{64, 2, 0};     // measured best for the 10k-event batch (wavefront-per-event kernel)
     hipStream_t capture = nullptr;
@@ -94,7 +103,7 @@ size_t vertex_lds(int tcap, int block) { return ((size_t)tcap * 24 + (size_t)64 
 
 int round_up(int v, int m) { return ((v + m - 1) / m) * m; }
 
-ds_status slot_for(ds_ctx *c, void *stream, int **counters)
+ds_status slot_for(ds_ctx *c, void *stream, int **counters, int *slot = nullptr)
 {
     auto it = c->slots.find(stream);
     int s;
@@ -106,6 +115,35 @@ ds_status slot_for(ds_ctx *c, void *stream, int **counters)
         s = it->second;
     }
     *counters = c->d_counters + 4 * s;
+    if (slot) *slot = s;
+    return DS_OK;
+}
+
+// The largest-first workspace of a stream slot for n events (grown on demand:
+// launches in flight may hold the old buffer, so the device is drained first,
+// and cached graphs that name it are dropped).
+ds_status order_workspace(ds_ctx *c, int slot, int n, int **ws)
+{
+    OrderWs &o = c->order_ws[slot];
+    if (o.cap < n) {
+        if (o.p) {
+            if (hipDeviceSynchronize() != hipSuccess) return DS_E_DEVICE;
+            for (auto &g : c->graphs) release_graph(g.second);
+            c->graphs.clear();
+            (void)hipFree(o.p);
+            o = OrderWs{};
+        }
+        const int cap = std::max(n, 1024);
+        int *p = nullptr;
+        if (hipMalloc(&p, sizeof(int) * ((size_t)ds::ORDER_WS + (size_t)cap)) != hipSuccess) return DS_E_NOMEM;
+        if (hipMemset(p, 0, sizeof(int) * (size_t)ds::ORDER_WS) != hipSuccess) {
+            (void)hipFree(p);
+            return DS_E_DEVICE;
+        }
+        o.p = p;
+        o.cap = cap;
+    }
+    *ws = o.p;
     return DS_OK;
 }
 
@@ -230,6 +268,8 @@ struct TrackPlan {
     ds::TrackArgs a;
     int block, grid;
     size_t lds;
+    int *order_ws = nullptr;   // persistent launch in largest-first order: its workspace
+    int n_cu = 256;
 };
 
 struct VertexPlan {
@@ -306,7 +346,26 @@ ds_status plan_track(ds_ctx *c, const ds_events *ev, const ds_tracks *out, int f
     p->block = block;
     p->grid = std::max(1, std::min(ev->n_events, c->n_cu * c->trk.wg_per_cu));
     p->lds = lds;
+    p->n_cu = c->n_cu;
+    p->order_ws = nullptr;
     return DS_OK;
+}
+
+// A persistent launch takes the events largest first when the context says so
+// (ws: the slot's workspace; the order kernels run ahead of the launch).
+void set_order(TrackPlan &p, int *ws)
+{
+    p.order_ws = ws;
+    p.a.order = ws ? ws + ds::ORDER_WS : nullptr;
+}
+
+ds_status plan_order(ds_ctx *c, int slot, int mode, TrackPlan &p)
+{
+    if (mode == DS_MODE_PER_EVENT || c->event_order != DS_ORDER_LARGEST_FIRST || p.a.n_events < 2) return DS_OK;
+    int *ws = nullptr;
+    const ds_status st = order_workspace(c, slot, p.a.n_events, &ws);
+    if (st == DS_OK) set_order(p, ws);
+    return st;
 }
 
 ds_status plan_vertex(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, float score_max, const ds_vertices *out,
@@ -432,6 +491,19 @@ hipError_t launch_clone(ds_ctx *c, const ds::CloneArgs &a, size_t lds, hipStream
     return hipGetLastError();
 }
 
+// The largest-first order of the batch into ws + ORDER_WS (two small launches).
+hipError_t launch_order(const ds::TrackArgs &a, int *ws, int n_cu, hipStream_t s)
+{
+    constexpr int B = 256;
+    const int grid = std::max(1, std::min((a.n_events + B - 1) / B, 4 * n_cu));
+    hipLaunchKernelGGL(ds::k_order_count<B>, dim3(grid), dim3(B), 0, s, a.seed_off, a.hit_off, a.n_events, ws);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(ds::k_order_place<B>, dim3(grid), dim3(B), 0, s, a.seed_off, a.hit_off, a.n_events, ws,
+                       ws + ds::ORDER_WS);
+    return hipGetLastError();
+}
+
 hipError_t run_track(ds_ctx *c, const TrackPlan &p, int mode, hipStream_t s)
 {
     if (mode == DS_MODE_PER_EVENT) {
@@ -442,6 +514,10 @@ hipError_t run_track(ds_ctx *c, const TrackPlan &p, int mode, hipStream_t s)
             if (err != hipSuccess) return err;
         }
         return hipSuccess;
+    }
+    if (p.a.order) {
+        hipError_t e = launch_order(p.a, p.order_ws, p.n_cu, s);
+        if (e != hipSuccess) return e;
     }
     return launch_track(p.block, p.a, c->G, p.grid, p.lds, s);
 }
@@ -562,6 +638,8 @@ void ds_destroy(ds_ctx *c)
     if (c->d_W) (void)hipFree(c->d_W);
     if (c->d_WL) (void)hipFree(c->d_WL);
     if (c->d_counters) (void)hipFree(c->d_counters);
+    for (auto &o : c->order_ws)
+        if (o.p) (void)hipFree(o.p);
     if (c->capture) (void)hipStreamDestroy(c->capture);
     delete c;
 }
@@ -669,11 +747,13 @@ ds_status ds_find_tracks(ds_ctx *c, const ds_events *ev, const ds_tracks *out, i
     std::lock_guard<std::mutex> lock(c->mu);
     if (hipSetDevice(c->device) != hipSuccess) return DS_E_DEVICE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    int *counters;
-    st = slot_for(c, stream, &counters);
+    int *counters, slot;
+    st = slot_for(c, stream, &counters, &slot);
     if (st != DS_OK) return st;
     TrackPlan p;
     st = plan_track(c, ev, out, fuse, counters, &p);
+    if (st != DS_OK) return st;
+    st = plan_order(c, slot, mode, p);
     if (st != DS_OK) return st;
     std::string key = graph_key(0, &p.a, sizeof(p.a), p.block, p.grid, p.lds);
     return run_maybe_graph(c, mode, key, s, [&](hipStream_t ss) { return run_track(c, p, mode, ss); });
@@ -826,12 +906,14 @@ ds_status ds_process(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, float
     std::lock_guard<std::mutex> lock(c->mu);
     if (hipSetDevice(c->device) != hipSuccess) return DS_E_DEVICE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    int *counters;
-    st = slot_for(c, stream, &counters);
+    int *counters, slot;
+    st = slot_for(c, stream, &counters, &slot);
     if (st != DS_OK) return st;
     const bool ck = c->clone_kill;
     TrackPlan tp;
     st = plan_track(c, ev, trk, ck ? 0 : 1, counters, &tp);
+    if (st != DS_OK) return st;
+    st = plan_order(c, slot, mode, tp);
     if (st != DS_OK) return st;
     VertexPlan vp;
     st = plan_vertex(c, ev, trk, score_max, out, counters, &vp);
@@ -848,6 +930,7 @@ ds_status ds_process(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, float
         TrackPlan fp;
         st = plan_track(c, ev, trk, 1, counters, &fp, true);
         if (st != DS_OK) return st;
+        set_order(fp, tp.order_ws);
         ds::TrackArgs &a = fp.a;
         a.score_max = score_max;
         a.vcap = out->cap_per_event;
@@ -910,6 +993,22 @@ ds_status ds_set_launch(ds_ctx *c, int kernel, int block, int wg_per_cu, int bin
     if (bins) n.bins = bins;
     if (kernel == 0 && (4 * n.bins) % n.block != 0) return DS_E_ARG;
     L = n;
+    return DS_OK;
+}
+
+ds_status ds_set_event_order(ds_ctx *c, int order)
+{
+    if (!c || (order != DS_ORDER_INPUT && order != DS_ORDER_LARGEST_FIRST)) return DS_E_ARG;
+    std::lock_guard<std::mutex> lock(c->mu);
+    c->event_order = order;
+    return DS_OK;
+}
+
+ds_status ds_get_event_order(ds_ctx *c, int *order)
+{
+    if (!c || !order) return DS_E_ARG;
+    std::lock_guard<std::mutex> lock(c->mu);
+    *order = c->event_order;
     return DS_OK;
 }
 

@@ -125,6 +125,7 @@ struct TrackArgs {
     int nb3, nbu3;       // the same for layer 3 (UTbX), stored after layers 0-2; Dv1 reads it
     float inv_bw3;       // by whole sectors only, so it has one u bin per sector
     const uint8_t *hsec; // Dv1: Y sector of every hit (null for Dv0)
+    const int *order;    // persistent launch: events in this order (a permutation), null = input order
 };
 
 struct GhostArgs {
@@ -1155,7 +1156,8 @@ __device__ __forceinline__ void vertex_event_block(const TrackArgs &a, const Dev
 __device__ __forceinline__ int grab_event(const TrackArgs &a, int iter)
 {
     if (a.ev_single >= 0) return iter == 0 ? a.ev_single : a.n_events;
-    return atomicAdd(&a.counter[0], 1);
+    const int k = atomicAdd(&a.counter[0], 1);
+    return (a.order && k < a.n_events) ? a.order[k] : k;
 }
 
 // One whole wave: the event of iteration `iter` and its offsets into LDS,
@@ -1608,6 +1610,89 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2
             __threadfence();
         }
     }
+}
+
+// ------------------------------------------------------------ event order
+//
+// Largest-first order of a batch for the persistent launch: uneven events
+// are taken from the work counter biggest first, so that the launch does not
+// end on one large event while the other workgroups idle.  A counting sort of
+// a work estimate (seeds + hits / 8, in bins of two, the top bin open-ended),
+// descending; events of one bin in any order (results do not depend on the
+// processing order).  Workspace ws: [0, ORDER_BINS) bin counts,
+// [ORDER_BINS, 2 ORDER_BINS) fill cursors, [2 ORDER_BINS] finished
+// workgroups of k_order_place; all zero between calls (the last workgroup of
+// k_order_place clears them).
+constexpr int ORDER_BINS = 1024;
+constexpr int ORDER_WS = 2 * ORDER_BINS + 64;   // ints ahead of the order array
+
+__device__ __forceinline__ int order_bin(const int *seed_off, const int *hit_off, int e)
+{
+    const int s = seed_off[e + 1] - seed_off[e];
+    const int h = hit_off[4 * e + 4] - hit_off[4 * e];
+    const int cost = max(s, 0) + max(h, 0) / 8;
+    return min(cost >> 1, ORDER_BINS - 1);
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_order_count(const int *seed_off, const int *hit_off, int n, int *ws)
+{
+    __shared__ int h[ORDER_BINS];
+    for (int b = threadIdx.x; b < ORDER_BINS; b += BLOCK) h[b] = 0;
+    __syncthreads();
+    for (int e = blockIdx.x * BLOCK + threadIdx.x; e < n; e += gridDim.x * BLOCK)
+        atomicAdd(&h[order_bin(seed_off, hit_off, e)], 1);
+    __syncthreads();
+    for (int b = threadIdx.x; b < ORDER_BINS; b += BLOCK)
+        if (h[b]) atomicAdd(&ws[b], h[b]);
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_order_place(const int *seed_off, const int *hit_off, int n, int *ws,
+                                                       int *order)
+{
+    static_assert(ORDER_BINS % BLOCK == 0, "whole bins per lane");
+    constexpr int PER = ORDER_BINS / BLOCK;
+    __shared__ int start[ORDER_BINS];
+    __shared__ int s_wsum[BLOCK / 64];
+    __shared__ int s_last;
+    const int t = threadIdx.x;
+    // lane t owns bins top - (t PER + j): a descending exclusive scan
+    int v[PER], sum = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        v[j] = ws[ORDER_BINS - 1 - (t * PER + j)];
+        sum += v[j];
+    }
+    int tot;
+    int excl = block_exclusive_scan<BLOCK>(sum, s_wsum, &tot);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        start[ORDER_BINS - 1 - (t * PER + j)] = excl;
+        excl += v[j];
+    }
+    __syncthreads();
+    for (int e = blockIdx.x * BLOCK + t; e < n; e += gridDim.x * BLOCK) {
+        const int b = order_bin(seed_off, hit_off, e);
+        const int pos = start[b] + atomicAdd(&ws[ORDER_BINS + b], 1);
+        if (pos < n) order[pos] = e;   // always, when the counts were zero on entry
+    }
+    __syncthreads();
+    if (t == 0) {
+        __threadfence();
+        s_last = atomicAdd(&ws[2 * ORDER_BINS], 1) == (int)gridDim.x - 1;
+    }
+    __syncthreads();
+    if (s_last) {
+        __threadfence();
+        for (int b = t; b < 2 * ORDER_BINS + 1; b += BLOCK) ws[b] = 0;
+    }
+}
+
+// Sets n ints to v (graph-safe: a kernel, not a memset node).
+__global__ void k_fill_i32(int *p, int v, int n)
+{
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) p[k] = v;
 }
 
 // Marks every candidate row empty (nhits 0) before a candidate-scoring pass.

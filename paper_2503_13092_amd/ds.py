@@ -20,11 +20,12 @@ LIB_PATH = os.path.join(HERE, "libds.so")
 DS_OK, DS_E_ARG, DS_E_STATE, DS_E_NOMEM, DS_E_CAPACITY, DS_E_DEVICE = range(6)
 DS_MODE_PER_EVENT, DS_MODE_PERSISTENT, DS_MODE_GRAPH = 0, 1, 2
 DS_F_BAD_OFFSETS, DS_F_CAPACITY, DS_F_NONFINITE = 1, 2, 4
+DS_ORDER_INPUT, DS_ORDER_LARGEST_FIRST = 0, 1
 N_WEIGHTS = 1121
 
 EXPORTED = ("ds_create", "ds_destroy", "ds_load_geometry", "ds_find_tracks", "ds_ghost_kill", "ds_kill_clones",
             "ds_candidate_slots", "ds_score_candidates", "ds_load_lines", "ds_vertex", "ds_process", "ds_set_launch",
-            "ds_get_launch", "ds_status_str")
+            "ds_get_launch", "ds_set_event_order", "ds_get_event_order", "ds_status_str")
 
 
 class DsGeometry(C.Structure):
@@ -123,6 +124,8 @@ def library() -> C.CDLL:
                                    C.c_int, P]
         lib.ds_set_launch.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int]
         lib.ds_get_launch.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        lib.ds_set_event_order.argtypes = [P, C.c_int]
+        lib.ds_get_event_order.argtypes = [P, C.POINTER(C.c_int)]
         lib.ds_status_str.argtypes = [C.c_int]
         lib.ds_status_str.restype = C.c_char_p
         for name in EXPORTED:
@@ -385,6 +388,16 @@ def ds_get_launch(ctx, kernel: int):
     b, w, n = C.c_int(), C.c_int(), C.c_int()
     _check(library().ds_get_launch(ctx, int(kernel), C.byref(b), C.byref(w), C.byref(n)), "ds_get_launch")
     return b.value, w.value, n.value
+
+
+def ds_set_event_order(ctx, order: int) -> None:
+    _check(library().ds_set_event_order(ctx, int(order)), "ds_set_event_order")
+
+
+def ds_get_event_order(ctx) -> int:
+    o = C.c_int()
+    _check(library().ds_get_event_order(ctx, C.byref(o)), "ds_get_event_order")
+    return o.value
 
 
 class Context:

@@ -342,6 +342,51 @@ def test_fused_process_graph_matches_oracle(ctx, config, n, cap):
     assert vc["n_ref"] + ref["vertices"]["overflow"] > (1000 if config == 4 else 0)
 
 
+def test_largest_first_order_matches_oracle_and_input_order():
+    """Largest-first event order (two sorting launches ahead of the
+    persistent launch): on uneven events every event is processed exactly
+    once, results equal the oracle's and are bitwise those of the input
+    order, in persistent and graph mode, on repeated calls (the sort's
+    workspace is clean again after each) and after the workspace has grown."""
+    c = ds.Context(0, G0, W)
+    try:
+        small = synth.generate(2, n_events=120, seed=71)
+        big = synth.generate(2, n_events=700, seed=72)
+        outs = {}
+        for order in (ds.DS_ORDER_INPUT, ds.DS_ORDER_LARGEST_FIRST):
+            ds.ds_set_event_order(c.handle, order)
+            assert ds.ds_get_event_order(c.handle) == order
+            for name, b in (("small", small), ("big", big), ("small2", small)):
+                for mode in (ds.DS_MODE_PERSISTENT, ds.DS_MODE_GRAPH):
+                    say(f"[order] order {order}, {name} ({b.n_events} events), mode {mode}")
+                    ev = ds.DeviceEvents(b)
+                    tr = ds.DeviceTracks(b.n_seeds)
+                    vt = ds.DeviceVertices(b.n_events, 256)
+                    for _ in range(2):
+                        vt.overflow.zero_()   # the library only adds to it
+                        ds.ds_process(c.handle, ev, tr, vt, mode, score_max=math.inf)
+                    torch.cuda.synchronize()
+                    outs[(order, name, mode)] = (tr.to_numpy(), vt.to_numpy())
+        for key, (gt, gv) in outs.items():
+            rt, rv = outs[(ds.DS_ORDER_INPUT, key[1], ds.DS_MODE_PERSISTENT)]
+            for k in ("x", "y", "tx", "ty", "qop", "chi2", "score", "hits", "nhits"):
+                assert np.array_equal(gt[k], rt[k]), (key, k)
+            for k in ("count", "i", "j", "x", "y", "z", "doca"):
+                assert np.array_equal(gv[k], rv[k]), (key, k)
+        gt, gv = outs[(ds.DS_ORDER_LARGEST_FIRST, "big", ds.DS_MODE_GRAPH)]
+        ref = O.run_path(big, G0, W, score_max=math.inf, cap=256, n_threads=8)
+        tc = parity.compare_tracks(gt, ref["tracks"])
+        found = ref["tracks"]["nhits"] > 0
+        sc = parity.compare_scores(gt["score"], ref["score"], found & (gt["nhits"] == ref["tracks"]["nhits"]))
+        vc = parity.compare_vertices(gv, ref["vertices"], G0["doca_max"], parity.excused_slot_set(big, tc, sc))
+        say(f"[order] largest first, 700 uneven events: identical {tc['identical']}/{tc['n']}, "
+            f"vertices {vc['n_gpu']}/{vc['n_ref']}")
+        assert vc["n_ref"] > 0
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+
+
 def _edge_event(rng, g, xs_ut, n_noise=40):
     """One hand-built event whose true tracks cross the UT near and beyond the
     hit-binning range |u| <= u_max: hits are forward-simulated from states

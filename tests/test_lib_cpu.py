@@ -80,6 +80,8 @@ def test_host_side_errors_without_gpu(lib):
     assert lib.ds_find_tracks(None, None, None, 1, 1, None) == ds.DS_E_ARG
     assert lib.ds_vertex(None, None, None, C.c_float(0.5), None, 1, None) == ds.DS_E_ARG
     assert lib.ds_set_launch(None, 0, 256, 4, 512) == ds.DS_E_ARG
+    assert lib.ds_set_event_order(None, ds.DS_ORDER_LARGEST_FIRST) == ds.DS_E_ARG
+    assert lib.ds_get_event_order(None, None) == ds.DS_E_ARG
     lib.ds_destroy(None)
 
 
