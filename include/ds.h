@@ -288,6 +288,23 @@ ds_status ds_process(ds_ctx *ctx, const ds_events *ev, const ds_tracks *trk, flo
                      const ds_vertices *out, int mode, void *hip_stream);
 
 /*
+ * ds_process without allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same step as ds_process in DS_MODE_PERSISTENT, with
+ * the same results, the event order set by ds_set_event_order, and no
+ * hipMalloc / hipFree or other allocation in the call.  Its work counters
+ * and largest-first order live in a static device array of the library
+ * (1.06 MB per device, held until the process ends), cleared at the start of
+ * each call by a fill kernel on hip_stream.  Every call on one device shares
+ * that array: calls that overlap on one device (on any streams or contexts)
+ * race and must not be issued.  The caller passes inputs and outputs as for
+ * ds_process.  DS_E_CAPACITY when n_events > DS_STATIC_MAX_EVENTS.
+ */
+#define DS_STATIC_MAX_EVENTS 262144
+ds_status ds_process_static(ds_ctx *ctx, const ds_events *ev, const ds_tracks *trk, float score_max,
+                            const ds_vertices *out, void *hip_stream);
+
+/*
  * Launch tuning (used by the autotuner).  kernel: 0 = tracking, 1 = vertexing.
  * block: threads per workgroup (64, 128, 256, 512); wg_per_cu: persistent
  * workgroups per compute unit (1..16); bins: hit bins per layer for the

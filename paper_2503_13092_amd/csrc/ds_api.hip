@@ -29,6 +29,10 @@ struct Launch {
     int block, wg_per_cu, bins;
 };
 
+constexpr int MAX_DEVICES = 64;
+constexpr int STATIC_HDR = 64;   // ints: [0, 2) tracking and [2, 4) vertexing work counters
+constexpr int STATIC_INTS = STATIC_HDR + ds::ORDER_WS + DS_STATIC_MAX_EVENTS;
+
 // Largest-first event order of one stream slot: ORDER_WS ints of bin counts
 // and cursors (zero between calls), then the order of up to `cap` events.
 struct OrderWs {
@@ -58,8 +62,39 @@ void release_graph(GraphEntry &g)
 
 }  // namespace
 
+// ds_process_static's workspace, for callers that cannot allocate: the work
+// counters, then the largest-first order's bins and cursors (ORDER_WS ints),
+// then the order of up to DS_STATIC_MAX_EVENTS events; 1.06 MB.  Every device
+// the library runs on holds its own copy until the process ends.  On the host
+// the name stands for no device address: host code uses only the address
+// static_scratch() looked up for the device.
+static __device__ __align__(256) int scratch[STATIC_INTS];
+
+namespace {
+
+std::mutex g_scratch_mu;
+int *g_scratch[MAX_DEVICES] = {};
+
+// The current device's copy of `scratch` (looked up once per device; the
+// device must be current).
+ds_status static_scratch(int device, int **p)
+{
+    if (device < 0 || device >= MAX_DEVICES) return DS_E_CAPACITY;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void *q = nullptr;
+        if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || !q) return DS_E_DEVICE;
+        g_scratch[device] = static_cast<int *>(q);
+    }
+    *p = g_scratch[device];
+    return DS_OK;
+}
+
+}  // namespace
+
 struct ds_ctx {
     int device = 0;
+    int *scratch = nullptr;    // this device's static workspace (ds_process_static)
     int n_cu = 256;
     bool loaded = false;
     ds::DevGeom G{};
@@ -585,6 +620,91 @@ std::string graph_key(int kind, const void *args, size_t n, int block, int grid,
     return key;
 }
 
+// Argument checks of ds_process / ds_process_static (host side, before any launch).
+ds_status check_process(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, const ds_vertices *out, int mode)
+{
+    if (!c) return DS_E_ARG;
+    if (!c->loaded) return DS_E_STATE;
+    if (mode < DS_MODE_PER_EVENT || mode > DS_MODE_GRAPH) return DS_E_ARG;
+    ds_status st = check_events(ev);
+    if (st != DS_OK) return st;
+    st = check_tracks(trk, ev->n_seeds, true);
+    if (st != DS_OK) return st;
+    if (!out || out->cap_per_event < 0 || !out->overflow || !out->flags) return DS_E_ARG;
+    if (ev->n_events == 0) return DS_OK;
+    if (!out->count) return DS_E_ARG;
+    if (out->cap_per_event > 0 && (!out->i || !out->j || !out->x || !out->y || !out->z || !out->doca))
+        return DS_E_ARG;
+    return check_extras(c, out);
+}
+
+// Enqueue the whole step on s: work counters at `counters` ([0, 2) tracking,
+// [2, 4) vertexing), the largest-first order in order_ws (null: input order).
+// Outside DS_MODE_GRAPH nothing here allocates (no graph keys are built).
+ds_status process_enqueue(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, float score_max,
+                          const ds_vertices *out, int mode, hipStream_t s, int *counters, int *order_ws)
+{
+    const bool ck = c->clone_kill;
+    TrackPlan tp;
+    ds_status st = plan_track(c, ev, trk, ck ? 0 : 1, counters, &tp);
+    if (st != DS_OK) return st;
+    if (mode != DS_MODE_PER_EVENT) set_order(tp, order_ws);
+    VertexPlan vp;
+    st = plan_vertex(c, ev, trk, score_max, out, counters, &vp);
+    if (st != DS_OK) return st;
+    ds::CloneArgs ca;
+    size_t clds = 0;
+    ds::GhostArgs ga = ghost_args(c, ev, trk);
+    if (ck) {
+        st = clone_args(ev, trk, &ca, &clds);
+        if (st != DS_OK) return st;
+    }
+    if (!ck && mode != DS_MODE_PER_EVENT) {
+        // one launch: tracking, ghost-killer and vertexing fused per event
+        TrackPlan fp;
+        st = plan_track(c, ev, trk, 1, counters, &fp, true);
+        if (st != DS_OK) return st;
+        set_order(fp, tp.order_ws);
+        ds::TrackArgs &a = fp.a;
+        a.score_max = score_max;
+        a.vcap = out->cap_per_event;
+        a.vcount = out->count;
+        a.vi = out->i;
+        a.vj = out->j;
+        a.vx = out->x;
+        a.vy = out->y;
+        a.vz = out->z;
+        a.vdoca = out->doca;
+        a.voverflow = out->overflow;
+        a.vflags = out->flags;
+        a.m_pipi = out->m_pipi;
+        a.m_ppi = out->m_ppi;
+        a.line0 = out->line[0];
+        a.line1 = out->line[1];
+        a.line2 = out->line[2];
+        a.line3 = out->line[3];
+        a.WL = c->d_WL;
+        auto body = [&](hipStream_t ss) { return run_track(c, fp, mode, ss); };
+        if (mode != DS_MODE_GRAPH) return dev_err(body(s));
+        return run_maybe_graph(c, mode, graph_key(5, &a, sizeof(a), fp.block, fp.grid, fp.lds), s, body);
+    }
+    auto body = [&](hipStream_t ss) {
+        hipError_t e = run_track(c, tp, mode, ss);
+        if (e != hipSuccess) return e;
+        if (ck) {
+            e = launch_clone(c, ca, clds, ss);
+            if (e != hipSuccess) return e;
+            e = launch_ghost(c, ga, ss);
+            if (e != hipSuccess) return e;
+        }
+        return run_vertex(c, vp, mode, ss);
+    };
+    if (mode != DS_MODE_GRAPH) return dev_err(body(s));
+    std::string key = graph_key(ck ? 4 : 2, &tp.a, sizeof(tp.a), tp.block, tp.grid, tp.lds);
+    key += graph_key(3, &vp.a, sizeof(vp.a), vp.block, vp.grid, vp.lds);
+    return run_maybe_graph(c, mode, key, s, body);
+}
+
 }  // namespace
 
 extern "C" {
@@ -615,6 +735,11 @@ ds_status ds_create(ds_ctx **ctx, int device)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->n_cu = prop.multiProcessorCount;
+    ds_status sst = static_scratch(device, &c->scratch);
+    if (sst != DS_OK) {
+        delete c;
+        return sst;
+    }
     if (hipMalloc(&c->d_counters, sizeof(int) * 4 * MAX_STREAM_SLOTS) != hipSuccess) {
         delete c;
         return DS_E_NOMEM;
@@ -888,84 +1013,42 @@ ds_status ds_vertex(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, float 
 ds_status ds_process(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, float score_max, const ds_vertices *out,
                      int mode, void *stream)
 {
-    if (!c) return DS_E_ARG;
-    if (!c->loaded) return DS_E_STATE;
-    if (mode < DS_MODE_PER_EVENT || mode > DS_MODE_GRAPH) return DS_E_ARG;
-    ds_status st = check_events(ev);
+    ds_status st = check_process(c, ev, trk, out, mode);
+    if (st != DS_OK || ev->n_events == 0) return st;
+    if (std::isnan(score_max)) score_max = (float)c->ghost_threshold;
+    std::lock_guard<std::mutex> lock(c->mu);
+    if (hipSetDevice(c->device) != hipSuccess) return DS_E_DEVICE;
+    int *counters, slot;
+    st = slot_for(c, stream, &counters, &slot);
     if (st != DS_OK) return st;
-    st = check_tracks(trk, ev->n_seeds, true);
+    int *order_ws = nullptr;
+    if (mode != DS_MODE_PER_EVENT && c->event_order == DS_ORDER_LARGEST_FIRST && ev->n_events >= 2) {
+        st = order_workspace(c, slot, ev->n_events, &order_ws);
+        if (st != DS_OK) return st;
+    }
+    return process_enqueue(c, ev, trk, score_max, out, mode, reinterpret_cast<hipStream_t>(stream), counters,
+                           order_ws);
+}
+
+ds_status ds_process_static(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, float score_max,
+                            const ds_vertices *out, void *stream)
+{
+    ds_status st = check_process(c, ev, trk, out, DS_MODE_PERSISTENT);
     if (st != DS_OK) return st;
-    if (!out || out->cap_per_event < 0 || !out->overflow || !out->flags) return DS_E_ARG;
+    if (ev->n_events > DS_STATIC_MAX_EVENTS) return DS_E_CAPACITY;
     if (ev->n_events == 0) return DS_OK;
-    if (!out->count) return DS_E_ARG;
-    if (out->cap_per_event > 0 && (!out->i || !out->j || !out->x || !out->y || !out->z || !out->doca))
-        return DS_E_ARG;
-    st = check_extras(c, out);
-    if (st != DS_OK) return st;
     if (std::isnan(score_max)) score_max = (float)c->ghost_threshold;
     std::lock_guard<std::mutex> lock(c->mu);
     if (hipSetDevice(c->device) != hipSuccess) return DS_E_DEVICE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    int *counters, slot;
-    st = slot_for(c, stream, &counters, &slot);
-    if (st != DS_OK) return st;
-    const bool ck = c->clone_kill;
-    TrackPlan tp;
-    st = plan_track(c, ev, trk, ck ? 0 : 1, counters, &tp);
-    if (st != DS_OK) return st;
-    st = plan_order(c, slot, mode, tp);
-    if (st != DS_OK) return st;
-    VertexPlan vp;
-    st = plan_vertex(c, ev, trk, score_max, out, counters, &vp);
-    if (st != DS_OK) return st;
-    ds::CloneArgs ca;
-    size_t clds = 0;
-    ds::GhostArgs ga = ghost_args(c, ev, trk);
-    if (ck) {
-        st = clone_args(ev, trk, &ca, &clds);
-        if (st != DS_OK) return st;
-    }
-    if (!ck && mode != DS_MODE_PER_EVENT) {
-        // one launch: tracking, ghost-killer and vertexing fused per event
-        TrackPlan fp;
-        st = plan_track(c, ev, trk, 1, counters, &fp, true);
-        if (st != DS_OK) return st;
-        set_order(fp, tp.order_ws);
-        ds::TrackArgs &a = fp.a;
-        a.score_max = score_max;
-        a.vcap = out->cap_per_event;
-        a.vcount = out->count;
-        a.vi = out->i;
-        a.vj = out->j;
-        a.vx = out->x;
-        a.vy = out->y;
-        a.vz = out->z;
-        a.vdoca = out->doca;
-        a.voverflow = out->overflow;
-        a.vflags = out->flags;
-        a.m_pipi = out->m_pipi;
-        a.m_ppi = out->m_ppi;
-        a.line0 = out->line[0];
-        a.line1 = out->line[1];
-        a.line2 = out->line[2];
-        a.line3 = out->line[3];
-        a.WL = c->d_WL;
-        std::string fkey = graph_key(5, &a, sizeof(a), fp.block, fp.grid, fp.lds);
-        return run_maybe_graph(c, mode, fkey, s, [&](hipStream_t ss) { return run_track(c, fp, mode, ss); });
-    }
-    std::string key = graph_key(ck ? 4 : 2, &tp.a, sizeof(tp.a), tp.block, tp.grid, tp.lds);
-    key += graph_key(3, &vp.a, sizeof(vp.a), vp.block, vp.grid, vp.lds);
-    return run_maybe_graph(c, mode, key, s, [&](hipStream_t ss) {
-        hipError_t e = run_track(c, tp, mode, ss);
-        if (e != hipSuccess) return e;
-        if (ck) {
-            e = launch_clone(c, ca, clds, ss);
-            if (e != hipSuccess) return e;
-            e = launch_ghost(c, ga, ss);
-            if (e != hipSuccess) return e;
-        }
-        return run_vertex(c, vp, mode, ss);
-    });
+    // the device's static array (its address, looked up at ds_create): work
+    // counters and order bins start at zero (a fill kernel, not a memset node,
+    // so that a caller may capture the call)
+    int *sp = c->scratch;
+    hipLaunchKernelGGL(ds::k_fill_i32, dim3(8), dim3(256), 0, s, sp, 0, STATIC_HDR + ds::ORDER_WS);
+    if (hipGetLastError() != hipSuccess) return DS_E_DEVICE;
+    int *order_ws = (c->event_order == DS_ORDER_LARGEST_FIRST && ev->n_events >= 2) ? sp + STATIC_HDR : nullptr;
+    return process_enqueue(c, ev, trk, score_max, out, DS_MODE_PERSISTENT, s, sp, order_ws);
 }
 
 ds_status ds_load_lines(ds_ctx *c, const float *w, size_t nw)

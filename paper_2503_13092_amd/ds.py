@@ -22,9 +22,10 @@ DS_MODE_PER_EVENT, DS_MODE_PERSISTENT, DS_MODE_GRAPH = 0, 1, 2
 DS_F_BAD_OFFSETS, DS_F_CAPACITY, DS_F_NONFINITE = 1, 2, 4
 DS_ORDER_INPUT, DS_ORDER_LARGEST_FIRST = 0, 1
 N_WEIGHTS = 1121
+DS_STATIC_MAX_EVENTS = 262144
 
 EXPORTED = ("ds_create", "ds_destroy", "ds_load_geometry", "ds_find_tracks", "ds_ghost_kill", "ds_kill_clones",
-            "ds_candidate_slots", "ds_score_candidates", "ds_load_lines", "ds_vertex", "ds_process", "ds_set_launch",
+            "ds_candidate_slots", "ds_score_candidates", "ds_load_lines", "ds_vertex", "ds_process", "ds_process_static", "ds_set_launch",
             "ds_get_launch", "ds_set_event_order", "ds_get_event_order", "ds_status_str")
 
 
@@ -122,6 +123,8 @@ def library() -> C.CDLL:
                                   C.c_int, P]
         lib.ds_process.argtypes = [P, C.POINTER(DsEvents), C.POINTER(DsTracks), C.c_float, C.POINTER(DsVertices),
                                    C.c_int, P]
+        lib.ds_process_static.argtypes = [P, C.POINTER(DsEvents), C.POINTER(DsTracks), C.c_float,
+                                          C.POINTER(DsVertices), P]
         lib.ds_set_launch.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int]
         lib.ds_get_launch.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
         lib.ds_set_event_order.argtypes = [P, C.c_int]
@@ -373,6 +376,12 @@ def ds_process(ctx, ev: DeviceEvents, trk: DeviceTracks, vtx: DeviceVertices, mo
                score_max: float = math.nan, stream=None) -> None:
     _check(library().ds_process(ctx, C.byref(ev.struct), C.byref(trk.struct), C.c_float(score_max),
                                 C.byref(vtx.struct), int(mode), _stream_handle(stream)), "ds_process")
+
+
+def ds_process_static(ctx, ev: DeviceEvents, trk: DeviceTracks, vtx: DeviceVertices, score_max: float = math.nan,
+                      stream=None) -> None:
+    _check(library().ds_process_static(ctx, C.byref(ev.struct), C.byref(trk.struct), C.c_float(score_max),
+                                       C.byref(vtx.struct), _stream_handle(stream)), "ds_process_static")
 
 
 def ds_load_lines(ctx, weights) -> None:
