@@ -334,6 +334,8 @@ ds_status plan_track(ds_ctx *c, const ds_events *ev, const ds_tracks *out, int f
     if (tcap > 65535) return DS_E_CAPACITY;
     size_t lds = track_lds(hcap, nb, nb3, block, icap, tcap);
     if (lds > LDS_LIMIT) return DS_E_CAPACITY;
+    // the network's feature tiles reuse the seed-constant ... item region
+    if (track_lds(0, 0, 0, block, icap, 0) - 16 < (size_t)(block / 64) * ds::MLP_TILE * 4) return DS_E_CAPACITY;
     ds::TrackArgs &a = p->a;
     std::memset(&a, 0, sizeof(a));
     a.n_events = ev->n_events;

@@ -419,25 +419,14 @@ __device__ __forceinline__ void mlp_lane_weights(const float *Wm, float w[MLP_LA
     }
 }
 
-// All 64 lanes must call it together (wave-uniform control flow).  Lanes with
-// row == false contribute zeros; every lane gets its own row's score.
-__device__ __forceinline__ float mlp_score_wave(const float w[MLP_LANE_WORDS], const float f[NF], bool row)
+// The network on operands already in the MFMA layout: x[4 s + b] holds, in
+// 16-lane group j, input 4 s + j of the row of lane 16 b + l % 16 (inputs past
+// the 17 features: the bias column 1, then zeros; all zeros for rows without
+// a track); rows: the ballot of the lanes with a row.  All 64 lanes call it
+// together.
+__device__ __forceinline__ float mlp_core(const float w[MLP_LANE_WORDS], const float x[MLP_K1], unsigned long long rows)
 {
-    const int lane = threadIdx.x & 63, grp = lane >> 4;
-    const unsigned long long rows = __ballot(row);
-    // layer-1 inputs padded to 20: the features, 1 (the bias column), zeros
-    float x[MLP_K1];
-#pragma unroll
-    for (int k = 0; k < MLP_K1; ++k) x[k] = (row && k < NF) ? f[k] : (row && k == NF) ? 1.0f : 0.0f;
-    // per step s, (register 4s + j, group b) -> (register 4s + b, group j): then
-    // x[4s + b] holds, in group j, input 4s + j of the row of lane 16 b + l % 16
-#pragma unroll
-    for (int s = 0; s < MLP_K1 / 4; ++s) {
-        lane_swap32(x[4 * s], x[4 * s + 2]);
-        lane_swap32(x[4 * s + 1], x[4 * s + 3]);
-        lane_swap16(x[4 * s], x[4 * s + 1]);
-        lane_swap16(x[4 * s + 2], x[4 * s + 3]);
-    }
+    const int grp = (threadIdx.x & 63) >> 4;
     float z = 0.0f;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
@@ -473,6 +462,67 @@ __device__ __forceinline__ float mlp_score_wave(const float w[MLP_LANE_WORDS], c
     }
     z += w[MLP_B3];
     return 1.0f / (1.0f + __expf(-z));
+}
+
+// The network on each lane's own 17 features f (registers).  All 64 lanes
+// must call it together (wave-uniform control flow).  Lanes with row == false
+// contribute zeros; every lane gets its own row's score.
+__device__ __forceinline__ float mlp_score_wave(const float w[MLP_LANE_WORDS], const float f[NF], bool row)
+{
+    const unsigned long long rows = __ballot(row);
+    // layer-1 inputs padded to 20: the features, 1 (the bias column), zeros
+    float x[MLP_K1];
+#pragma unroll
+    for (int k = 0; k < MLP_K1; ++k) x[k] = (row && k < NF) ? f[k] : (row && k == NF) ? 1.0f : 0.0f;
+    // per step s, (register 4s + j, group b) -> (register 4s + b, group j): then
+    // x[4s + b] holds, in group j, input 4s + j of the row of lane 16 b + l % 16
+#pragma unroll
+    for (int s = 0; s < MLP_K1 / 4; ++s) {
+        lane_swap32(x[4 * s], x[4 * s + 2]);
+        lane_swap32(x[4 * s + 1], x[4 * s + 3]);
+        lane_swap16(x[4 * s], x[4 * s + 1]);
+        lane_swap16(x[4 * s + 2], x[4 * s + 3]);
+    }
+    return mlp_core(w, x, rows);
+}
+
+// A wavefront's feature tile in LDS, already in the operand layout: feature k
+// of the row of lane l at T[k * 64 + 4 (l % 16) + l / 16], so that a lane of
+// group j reads inputs 4 s + j of its four row blocks as one 16-byte word.
+constexpr int MLP_TILE = NF * 64;   // floats per wavefront
+
+__device__ __forceinline__ int mlp_tile_pos(int lane) { return 4 * (lane & 15) + (lane >> 4); }
+
+// Row of this lane into the tile (zeros for a lane without a row).
+__device__ __forceinline__ void mlp_tile_store(float *T, const float f[NF], bool row)
+{
+    const int pos = mlp_tile_pos(threadIdx.x & 63);
+#pragma unroll
+    for (int k = 0; k < NF; ++k) T[k * 64 + pos] = row ? f[k] : 0.0f;
+}
+
+// The network on the wavefront's tile T (written by mlp_tile_store of every
+// lane of this wavefront: a wavefront's LDS operations complete in order).
+__device__ __forceinline__ float mlp_score_tile(const float w[MLP_LANE_WORDS], const float *T, bool row)
+{
+    const int lane = threadIdx.x & 63, grp = lane >> 4, r = lane & 15;
+    const unsigned long long rows = __ballot(row);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);   // the tile's stores stay ahead of the loads
+    float x[MLP_K1];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const f32x4 v = *reinterpret_cast<const f32x4 *>(T + (4 * s + grp) * 64 + 4 * r);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) x[4 * s + b] = v[b];
+    }
+    // inputs 16..19: feature 16 (group 0), the bias column (group 1), zeros
+    const f32x4 v = *reinterpret_cast<const f32x4 *>(T + 16 * 64 + 4 * r);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const float bias = ((rows >> (16 * b + r)) & 1ull) ? 1.0f : 0.0f;
+        x[16 + b] = grp == 0 ? v[b] : (grp == 1 ? bias : 0.0f);
+    }
+    return mlp_core(w, x, rows);
 }
 
 // ------------------------------------------------------------------ track
@@ -695,11 +745,15 @@ __device__ __forceinline__ void item_candidates_n(const DevGeom &G, const TrackA
         }
         maxlen = max(maxlen, len[L]);
     }
-    // the three layers advance together: one LDS round trip per step; the two
-    // best keep (|delta|, position), u and index are re-read only on ties
-    double d0[3] = {INFINITY, INFINITY, INFINITY}, d1[3] = {INFINITY, INFINITY, INFINITY};
+    // the three layers advance together: one LDS round trip per step.  The
+    // kept hits are held as (float32-rounded |delta|, LDS position): rounding
+    // is monotone, so a strictly smaller rounded distance is a strictly
+    // smaller distance; equal rounded distances (exact ties included) are
+    // settled on the full key (|delta| in float64, u, index, re-read from LDS)
+    // on a path of their own, taken by the whole wavefront when any lane
+    // needs it.  Window membership is always the float64 test.
+    float f0[3] = {INFINITY, INFINITY, INFINITY}, f1[3] = {INFINITY, INFINITY, INFINITY};
     int p0k[3] = {-1, -1, -1}, p1k[3] = {-1, -1, -1};
-    float u0k[3] = {0.0f, 0.0f, 0.0f}, u1k[3] = {0.0f, 0.0f, 0.0f};   // their u, for the residuals
     for (int k = 0; k < maxlen; ++k) {
         // the three loads first (a finished layer re-reads its start), then the tests
         int pp[3];
@@ -710,29 +764,55 @@ __device__ __forceinline__ void item_candidates_n(const DevGeom &G, const TrackA
             pp[L] = (!DV1 || kk < len0[L]) ? lo[L] + kk : lo1[L] + (kk - len0[L]);
             uu[L] = hu_s[pp[L]];
         }
+        double dd[3];
+        float fd[3];
+        bool in[3], lt0[3], lt1[3], eq[3];
+        bool any_eq = false;
 #pragma unroll
         for (int L = 0; L < 3; ++L) {
-            if (k >= len[L]) continue;
-            const int p = pp[L];
-            const float u = uu[L];
-            const double d = fabs((double)u - m[L]);
-            if (!(d <= W2)) continue;
             const int NL = L == 0 ? N0 : (L == 1 ? N1 : N2);
-            if (before(hu_s, hidx_s, d, u, p, d0[L], p0k[L])) {
-                if (NL > 1) {
-                    d1[L] = d0[L];
-                    p1k[L] = p0k[L];
-                    u1k[L] = u0k[L];
+            dd[L] = fabs((double)uu[L] - m[L]);
+            fd[L] = (float)dd[L];
+            in[L] = (k < len[L]) & (dd[L] <= W2);
+            lt0[L] = in[L] & (fd[L] < f0[L]);
+            lt1[L] = (NL > 1) & in[L] & !lt0[L] & (fd[L] < f1[L]);
+            eq[L] = in[L] & ((fd[L] == f0[L]) | ((NL > 1) & (fd[L] == f1[L])));
+            any_eq |= eq[L];
+        }
+        if (__builtin_expect(__ballot(any_eq) != 0ull, 0)) {
+#pragma unroll
+            for (int L = 0; L < 3; ++L) {
+                const int NL = L == 0 ? N0 : (L == 1 ? N1 : N2);
+                if (eq[L]) {
+                    const double e0 = p0k[L] >= 0 ? fabs((double)hu_s[p0k[L]] - m[L]) : INFINITY;
+                    lt0[L] = before(hu_s, hidx_s, dd[L], uu[L], pp[L], e0, p0k[L]);
+                    if (NL > 1) {
+                        const double e1 = p1k[L] >= 0 ? fabs((double)hu_s[p1k[L]] - m[L]) : INFINITY;
+                        lt1[L] = !lt0[L] && before(hu_s, hidx_s, dd[L], uu[L], pp[L], e1, p1k[L]);
+                    }
                 }
-                d0[L] = d;
-                p0k[L] = p;
-                u0k[L] = u;
-            } else if (NL > 1 && before(hu_s, hidx_s, d, u, p, d1[L], p1k[L])) {
-                d1[L] = d;
-                p1k[L] = p;
-                u1k[L] = u;
             }
         }
+#pragma unroll
+        for (int L = 0; L < 3; ++L) {
+            const int NL = L == 0 ? N0 : (L == 1 ? N1 : N2);
+            if (NL > 1) {   // lt0 and lt1 exclude each other
+                f1[L] = lt1[L] ? fd[L] : f1[L];
+                p1k[L] = lt1[L] ? pp[L] : p1k[L];
+                f1[L] = lt0[L] ? f0[L] : f1[L];
+                p1k[L] = lt0[L] ? p0k[L] : p1k[L];
+            }
+            f0[L] = lt0[L] ? fd[L] : f0[L];
+            p0k[L] = lt0[L] ? pp[L] : p0k[L];
+        }
+    }
+    // u of the kept hits, for the residuals
+    float u0k[3], u1k[3];
+#pragma unroll
+    for (int L = 0; L < 3; ++L) {
+        const int NL = L == 0 ? N0 : (L == 1 ? N1 : N2);
+        u0k[L] = hu_s[p0k[L] >= 0 ? p0k[L] : p3];
+        u1k[L] = NL > 1 ? hu_s[p1k[L] >= 0 ? p1k[L] : p3] : 0.0f;
     }
     int A[3][MAX_CLOSEST];
     int nA[3];
@@ -932,17 +1012,45 @@ __device__ __forceinline__ void write_candidate_row(const TrackArgs &a, const De
     a.r_chi2[r] = t.chi2;
 }
 
+// The launch's binning parameters, read once per event and held in scalar
+// registers (opaque to the compiler, which would otherwise re-load them from
+// the argument segment, a scalar round trip, at every use).
+struct BinParams {
+    int nb, nbu, nb3, nbu3;
+    float u0, inv_bw, inv_bw3;
+};
+
+template <typename T>
+__device__ __forceinline__ T opaque_uniform(T v)
+{
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
+__device__ __forceinline__ BinParams bin_params(const TrackArgs &a)
+{
+    BinParams b;
+    b.nb = opaque_uniform(a.nb);
+    b.nbu = opaque_uniform(a.nbu);
+    b.nb3 = opaque_uniform(a.nb3);
+    b.nbu3 = opaque_uniform(a.nbu3);
+    b.u0 = opaque_uniform(a.u0);
+    b.inv_bw = opaque_uniform(a.inv_bw);
+    b.inv_bw3 = opaque_uniform(a.inv_bw3);
+    return b;
+}
+
 // Bucket of a hit: (layer, u bin) for Dv0; (layer, Y sector, u bin) for Dv1,
 // with one last bucket per layer for sector ids outside [0, nsec).
 template <bool DV1>
-__device__ __forceinline__ int hit_bucket(const TrackArgs &a, int nsec, int L, float u, int k)
+__device__ __forceinline__ int hit_bucket(const TrackArgs &a, const BinParams &bp, int nsec, int L, float u, int k)
 {
     const bool l3 = DV1 && L == 3;   // Dv0's layer 3 has the common layout
-    const int nbu = l3 ? a.nbu3 : a.nbu;
-    int b = L * a.nb + bin_of(u, a.u0, l3 ? a.inv_bw3 : a.inv_bw, nbu);
+    const int nbu = l3 ? bp.nbu3 : bp.nbu;
+    int b = L * bp.nb + bin_of(u, bp.u0, l3 ? bp.inv_bw3 : bp.inv_bw, nbu);
     if (DV1) {
         const int sec = a.hsec[k];
-        b = sec < nsec ? b + sec * nbu : L * a.nb + nsec * nbu;
+        b = sec < nsec ? b + sec * nbu : L * bp.nb + nsec * nbu;
     }
     return b;
 }
@@ -974,6 +1082,7 @@ __device__ __forceinline__ bool stage_hits_w(const TrackArgs &a, int nsec, int h
     }
     if (tid == 0) E[0] = 0;
     between();
+    const BinParams bp = bin_params(a);
     bool bad = false;
     for (; L < 4; L += NW) {
         if (L != wave) {   // a further layer of this wavefront (fewer than four wavefronts)
@@ -985,8 +1094,8 @@ __device__ __forceinline__ bool stage_hits_w(const TrackArgs &a, int nsec, int h
                 u[j] = (k < n) ? a.hu[hb + lo + k] : 0.0f;
             }
         }
-        int *EL = E + 1 + L * a.nb;   // EL[b]: count, then end, of bucket (L, b)
-        const int nb = (DV1 && L == 3) ? a.nb3 : a.nb;
+        int *EL = E + 1 + L * bp.nb;   // EL[b]: count, then end, of bucket (L, b)
+        const int nb = (DV1 && L == 3) ? bp.nb3 : bp.nb;
         for (int b = lane; b < nb; b += 64) EL[b] = 0;
         const int rounds = (n + 64 * HPT - 1) / (64 * HPT);
         for (int r = 0; r < rounds; ++r) {
@@ -1003,7 +1112,7 @@ __device__ __forceinline__ bool stage_hits_w(const TrackArgs &a, int nsec, int h
                 const int k = r * 64 * HPT + lane + 64 * j;
                 if (k < n) {
                     if (!isfinite(u[j])) bad = true;
-                    else atomicAdd(&E[hit_bucket<DV1>(a, nsec, L, u[j], hb + lo + k) + 1], 1);
+                    else atomicAdd(&E[hit_bucket<DV1>(a, bp, nsec, L, u[j], hb + lo + k) + 1], 1);
                 }
             }
         }
@@ -1044,7 +1153,7 @@ __device__ __forceinline__ bool stage_hits_w(const TrackArgs &a, int nsec, int h
                 if (r * 64 * HPT + 64 * j >= n) break;
                 const int k = r * 64 * HPT + lane + 64 * j;
                 if (k < n && isfinite(u[j])) {
-                    const int pos = atomicAdd(&E[hit_bucket<DV1>(a, nsec, L, u[j], hb + lo + k) + 1], 1);
+                    const int pos = atomicAdd(&E[hit_bucket<DV1>(a, bp, nsec, L, u[j], hb + lo + k) + 1], 1);
                     hu_s[pos] = u[j];
                     hidx_s[pos] = (uint16_t)k;
                 }
@@ -1532,7 +1641,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2
             // network run by each wavefront with a winner as a whole
             bool won = false;
             StoredTrack t;
-            float f[NF];
+            int wbp[4] = {-1, -1, -1, -1};
             if (!CANDS && tid < nacc) {
                 const int per_r3 = G.nw[0] * G.nw[1] * G.nw[2];
                 const unsigned long long key = s_key[tid];
@@ -1565,17 +1674,38 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2
                         const int v = (int)((hp >> (16 * L)) & 0xffffull);
                         bp[L] = v == 0xffff ? -1 : v;
                     }
-                    t = write_track(a, G, i, sd, s_c[tid], hu_s, hidx_s, bp, cw, a.fuse_mlp ? f : nullptr);
+                    t = write_track(a, G, i, sd, s_c[tid], hu_s, hidx_s, bp, cw, nullptr);
                     won = true;
+#pragma unroll
+                    for (int L = 0; L < 4; ++L) wbp[L] = bp[L];
                 }
             }
-            if (!CANDS && a.fuse_mlp && __ballot(won) != 0) {
-                float mw[MLP_LANE_WORDS];
-                mlp_lane_weights(a.W, mw);
-                const float sc_ = mlp_score_wave(mw, f, won);
-                if (won) {
-                    t.score = sc_;
-                    a.score[i] = sc_;
+            if (!CANDS && a.fuse_mlp) {
+                // the chunk's seed constants, keys and items are read: each
+                // wavefront's feature tile goes there, and the network reads it
+                lds_barrier();
+                if (__ballot(won) != 0) {
+                    float *T = reinterpret_cast<float *>(s_c) + (tid >> 6) * MLP_TILE;
+                    float f[NF];
+                    if (won) {
+                        float hu4[4];
+                        int mask = 0;
+#pragma unroll
+                        for (int L = 0; L < 4; ++L) {
+                            hu4[L] = wbp[L] >= 0 ? hu_s[wbp[L]] : 0.0f;
+                            mask |= wbp[L] >= 0 ? (1 << L) : 0;
+                        }
+                        ghost_features(G, t.x, t.y, t.tx, t.ty, t.qop, t.chi2, __popc(mask), sd.x, sd.y, sd.tx, sd.ty,
+                                       sd.qop, hu4, mask, f);
+                    }
+                    mlp_tile_store(T, f, won);
+                    float mw[MLP_LANE_WORDS];
+                    mlp_lane_weights(a.W, mw);
+                    const float sc_ = mlp_score_tile(mw, T, won);
+                    if (won) {
+                        t.score = sc_;
+                        a.score[i] = sc_;
+                    }
                 }
             }
             const bool kept = VTX && won && t.score < a.score_max;
