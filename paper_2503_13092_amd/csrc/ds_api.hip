@@ -108,7 +108,7 @@ struct ds_ctx {
     std::map<void *, int> slots;
     OrderWs order_ws[MAX_STREAM_SLOTS];
     int event_order = DS_ORDER_INPUT;   // persistent launches: DS_ORDER_*
-    Launch trk{256, 3, 512};  // three resident workgroups per CU (168 VGPRs, ~50 KB LDS): one grid wave
+    Launch trk{256, 3, 1024};  // three resident workgroups per CU (168 VGPRs, ~50 KB LDS): one grid wave
     Launch vtx{64, 2, 0};     // measured best for the 10k-event batch (wavefront-per-event kernel)
     hipStream_t capture = nullptr;
     std::map<std::string, GraphEntry> graphs;
@@ -126,7 +126,7 @@ size_t track_lds(int hcap, int nb, int nb3, int block, int icap, int tcap)
 {
     size_t off = (size_t)hcap * 4;
     off = round16(off + (size_t)hcap * 2);
-    off = round16(off + (size_t)(3 * nb + nb3 + 1) * 4);
+    off = round16(off + (size_t)(3 * nb + nb3 + 1) * 2);
     off += (size_t)block * sizeof(ds::SeedConst);
     off += (size_t)block * 8;
     off = round16(off + (size_t)block * 4);
@@ -327,6 +327,7 @@ ds_status plan_track(ds_ctx *c, const ds_events *ev, const ds_tracks *out, int f
     const int nb = dv1 ? nsec * nbu + 1 : nbu;
     const int nbu3 = dv1 ? 1 : nbu, nb3 = dv1 ? nsec + 1 : nb;
     int hcap = round_up(std::max(ev->max_hits_per_event, 1), 64);
+    if (hcap > 65535) return DS_E_CAPACITY;   // 16-bit LDS positions and bucket bounds
     const int block = c->trk.block;
     // items per chunk: room for ITEMS_PER_SEED per seed; a chunk shrinks when its seeds need more
     const int icap = std::max(block * ITEMS_PER_SEED, ds::MAX_L3);

@@ -262,7 +262,7 @@ __device__ __forceinline__ bool before(const float *hu_s, const uint16_t *hidx_s
 
 // LDS positions [p_lo, p_hi) of the buckets of `layer` covering [m - W, m + W]
 // (a superset of the window: membership is decided on |u - m| <= W).
-__device__ __forceinline__ void bin_range(const int *E, int layer, int nb, float u0, float inv_bw, double m, double W,
+__device__ __forceinline__ void bin_range(const uint16_t *E, int layer, int nb, float u0, float inv_bw, double m, double W,
                                  int &p_lo, int &p_hi)
 {
     const int b_lo = bin_of((float)(m - W - 1e-3), u0, inv_bw, nb);
@@ -617,7 +617,7 @@ __device__ __forceinline__ void sector_span(const SeedConst &sc, int L, int &klo
 // u bins cover [m - W, m + W]; buckets are (layer, sector, u bin).  Branch-free:
 // the four bounds are read at sector indices clamped into the layer's buckets
 // and dropped when the sector is not in the span.
-__device__ __forceinline__ void sector_bins(const int *E, const TrackArgs &a, int nsec, int L, int klo, int khi, double m,
+__device__ __forceinline__ void sector_bins(const uint16_t *E, const TrackArgs &a, int nsec, int L, int klo, int khi, double m,
                                    double W, int &lo0, int &len0, int &lo1, int &len1)
 {
     const int b_lo = bin_of((float)(m - W - 1e-3), a.u0, a.inv_bw, a.nbu);
@@ -643,7 +643,7 @@ struct TripletProbe {
     bool hit;
 };
 
-__device__ __forceinline__ TripletProbe dv1_probe(const DevGeom &G, const TrackArgs &a, const float *hu_s, const int *E,
+__device__ __forceinline__ TripletProbe dv1_probe(const DevGeom &G, const TrackArgs &a, const float *hu_s, const uint16_t *E,
                                          const SeedConst &sc, int k0lo, int k0hi, double W, int p3)
 {
     TripletProbe t;
@@ -661,7 +661,7 @@ __device__ __forceinline__ TripletProbe dv1_probe(const DevGeom &G, const TrackA
 // projections, the eight bucket bounds, the first four UTaX positions of each
 // window), so that each stage costs one LDS round trip for both; a window
 // holding more than four hits is finished by dv1_rest.
-__device__ __forceinline__ void dv1_probe_pair(const DevGeom &G, const TrackArgs &a, const float *hu_s, const int *E,
+__device__ __forceinline__ void dv1_probe_pair(const DevGeom &G, const TrackArgs &a, const float *hu_s, const uint16_t *E,
                                       const SeedConst &sa, const SeedConst &sb, int ka_lo, int ka_hi, int kb_lo,
                                       int kb_hi, double Wa, double Wb, int pa3, int pb3, TripletProbe &ta,
                                       TripletProbe &tb)
@@ -701,7 +701,7 @@ __device__ __forceinline__ bool dv1_rest(const float *hu_s, const TripletProbe &
     return hit;
 }
 
-__device__ __forceinline__ bool dv1_triplet(const DevGeom &G, const TrackArgs &a, const float *hu_s, const int *E,
+__device__ __forceinline__ bool dv1_triplet(const DevGeom &G, const TrackArgs &a, const float *hu_s, const uint16_t *E,
                                    const SeedConst &sc, int k0lo, int k0hi, double W, int p3)
 {
     return dv1_rest(hu_s, dv1_probe(G, a, hu_s, E, sc, k0lo, k0hi, W, p3), W, 2);
@@ -720,7 +720,7 @@ __device__ __forceinline__ unsigned long long pack_key_dv1(int n, double chi2, i
 // tuples, their fits.  visit(n, c, alpha, beta, chi2, bp) is called for each.
 template <int N0, int N1, int N2, bool DV1, typename Visit>
 __device__ __forceinline__ void item_candidates_n(const DevGeom &G, const TrackArgs &a, const float *hu_s,
-                                       const uint16_t *hidx_s, const int *E, const SeedConst &sc, int cb, int p3,
+                                       const uint16_t *hidx_s, const uint16_t *E, const SeedConst &sc, int cb, int p3,
                                        Visit &&visit)
 {
     const double W2 = fma(G.w2c1, fabs((double)sc.q), G.w2c0);
@@ -861,7 +861,7 @@ __device__ __forceinline__ void item_candidates_n(const DevGeom &G, const TrackA
 // cb: the UTbX hit's rank in its window (Dv0) or its index in its layer run (Dv1).
 template <bool DV1 = false, typename Visit>
 __device__ __forceinline__ void item_candidates(const DevGeom &G, const TrackArgs &a, const float *hu_s,
-                                       const uint16_t *hidx_s, const int *E, const SeedConst &sc, int cb, int p3,
+                                       const uint16_t *hidx_s, const uint16_t *E, const SeedConst &sc, int cb, int p3,
                                        Visit &&visit)
 {
     if (G.ncl[0] == 1 && G.ncl[1] == 2 && G.ncl[2] == 2)
@@ -900,7 +900,7 @@ __device__ __forceinline__ int first_window_rank(const DevGeom &G, const float *
 // Best candidate through one UTbX hit: more hits, then lower chi2, then lower index.
 template <bool DV1 = false>
 __device__ __forceinline__ void item_best(const DevGeom &G, const TrackArgs &a, const float *hu_s, const uint16_t *hidx_s,
-                                 const int *E, const SeedConst &sc, int cb, int p3, int &best_n, double &best_chi2,
+                                 const uint16_t *E, const SeedConst &sc, int cb, int p3, int &best_n, double &best_chi2,
                                  int &best_c, int bp_out[4])
 {
     best_n = 0;
@@ -1057,6 +1057,17 @@ __device__ __forceinline__ int hit_bucket(const TrackArgs &a, const BinParams &b
 
 constexpr int STAGE_HPT = 16;   // hits per lane per staging round
 
+// Bucket bounds are 16-bit (an event's hits in LDS stay below 2^16): E[i] += 1
+// through a 32-bit LDS atomic on the pair of bounds that holds it, returning
+// the old E[i]; the low half never reaches 2^16, so it never carries into the
+// high one.
+__device__ __forceinline__ int bkt_add(uint16_t *E, int i)
+{
+    uint32_t *w = reinterpret_cast<uint32_t *>(E) + (i >> 1);
+    const int sh = (i & 1) * 16;
+    return (int)((atomicAdd(w, 1u << sh) >> sh) & 0xffffu);
+}
+
 // Stage one event's hits a wavefront per layer: each wavefront counts its
 // layer's hits into the layer's buckets, scans them (64 buckets per step, DPP
 // sums) and places the hits, with no workgroup barrier until the end: a
@@ -1065,7 +1076,7 @@ constexpr int STAGE_HPT = 16;   // hits per lane per staging round
 // on entry.
 template <int BLOCK, bool DV1, typename Between>
 __device__ __forceinline__ bool stage_hits_w(const TrackArgs &a, int nsec, int hb, const int hl[4], int nh,
-                                             float *hu_s, uint16_t *hidx_s, int *E, int *s_bad, Between &&between)
+                                             float *hu_s, uint16_t *hidx_s, uint16_t *E, int *s_bad, Between &&between)
 {
     constexpr int HPT = STAGE_HPT;
     constexpr int NW = BLOCK / 64;
@@ -1094,7 +1105,7 @@ __device__ __forceinline__ bool stage_hits_w(const TrackArgs &a, int nsec, int h
                 u[j] = (k < n) ? a.hu[hb + lo + k] : 0.0f;
             }
         }
-        int *EL = E + 1 + L * bp.nb;   // EL[b]: count, then end, of bucket (L, b)
+        uint16_t *EL = E + 1 + L * bp.nb;   // EL[b]: count, then end, of bucket (L, b)
         const int nb = (DV1 && L == 3) ? bp.nb3 : bp.nb;
         for (int b = lane; b < nb; b += 64) EL[b] = 0;
         const int rounds = (n + 64 * HPT - 1) / (64 * HPT);
@@ -1112,31 +1123,23 @@ __device__ __forceinline__ bool stage_hits_w(const TrackArgs &a, int nsec, int h
                 const int k = r * 64 * HPT + lane + 64 * j;
                 if (k < n) {
                     if (!isfinite(u[j])) bad = true;
-                    else atomicAdd(&E[hit_bucket<DV1>(a, bp, nsec, L, u[j], hb + lo + k) + 1], 1);
+                    else bkt_add(E, hit_bucket<DV1>(a, bp, nsec, L, u[j], hb + lo + k) + 1);
                 }
             }
         }
-        // exclusive prefix over the layer's buckets, offset by the layer's start;
-        // up to 512 buckets: eight independent wavefront scans, then the carries
+        // exclusive prefix over the layer's buckets, offset by the layer's start:
+        // 512 buckets at a time, eight independent wavefront scans, then the carries
         int carry = lo;
-        if (nb <= 512) {
+        for (int b0 = 0; b0 < nb; b0 += 512) {
             int v[8], incl[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = 64 * j + lane < nb ? EL[64 * j + lane] : 0;
+            for (int j = 0; j < 8; ++j) v[j] = b0 + 64 * j + lane < nb ? (int)EL[b0 + 64 * j + lane] : 0;
 #pragma unroll
             for (int j = 0; j < 8; ++j) incl[j] = wave_inclusive_sum(v[j]);
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                if (64 * j + lane < nb) EL[64 * j + lane] = carry + incl[j] - v[j];
+                if (b0 + 64 * j + lane < nb) EL[b0 + 64 * j + lane] = (uint16_t)(carry + incl[j] - v[j]);
                 carry += __builtin_amdgcn_readlane(incl[j], 63);
-            }
-        } else {
-            for (int b0 = 0; b0 < nb; b0 += 64) {
-                const int b = b0 + lane;
-                const int v1 = b < nb ? EL[b] : 0;
-                const int incl1 = wave_inclusive_sum(v1);
-                if (b < nb) EL[b] = carry + incl1 - v1;
-                carry += __builtin_amdgcn_readlane(incl1, 63);
             }
         }
         // placing pass: EL[b] advances to the end of bucket b
@@ -1153,7 +1156,7 @@ __device__ __forceinline__ bool stage_hits_w(const TrackArgs &a, int nsec, int h
                 if (r * 64 * HPT + 64 * j >= n) break;
                 const int k = r * 64 * HPT + lane + 64 * j;
                 if (k < n && isfinite(u[j])) {
-                    const int pos = atomicAdd(&E[hit_bucket<DV1>(a, bp, nsec, L, u[j], hb + lo + k) + 1], 1);
+                    const int pos = bkt_add(E, hit_bucket<DV1>(a, bp, nsec, L, u[j], hb + lo + k) + 1);
                     hu_s[pos] = u[j];
                     hidx_s[pos] = (uint16_t)k;
                 }
@@ -1293,8 +1296,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2
     off += (size_t)a0.hcap * 4;
     uint16_t *hidx_s = reinterpret_cast<uint16_t *>(smem + off);
     off = (off + (size_t)a0.hcap * 2 + 15) & ~(size_t)15;
-    int *E = reinterpret_cast<int *>(smem + off);
-    off = (off + (size_t)(3 * a0.nb + a0.nb3 + 1) * 4 + 15) & ~(size_t)15;
+    uint16_t *E = reinterpret_cast<uint16_t *>(smem + off);
+    off = (off + (size_t)(3 * a0.nb + a0.nb3 + 1) * 2 + 15) & ~(size_t)15;
     SeedConst *s_c = reinterpret_cast<SeedConst *>(smem + off);
     off += (size_t)BLOCK * sizeof(SeedConst);
     unsigned long long *s_key = reinterpret_cast<unsigned long long *>(smem + off);
