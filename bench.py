@@ -106,6 +106,12 @@ def cpu_baseline(batch, g, w):
                 single_thread_events_per_s=round(1.0 / per_event, 1))
 
 
+def launch_settings(ds, ctx):
+    block, wpc, bins = ds.ds_get_launch(ctx, 0)
+    return dict(block=block, wg_per_cu=wpc, bins=bins,
+                order="largest_first" if ds.ds_get_event_order(ctx) == ds.DS_ORDER_LARGEST_FIRST else "input")
+
+
 def copy_ceiling_gbs(torch, nbytes=2 << 30, reps=10):
     """Achievable HBM bandwidth of a plain device-to-device copy (read + write)."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -165,7 +171,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2503_13092_amd import ds, synth
+    from paper_2503_13092_amd import autotune, ds, synth
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -180,6 +186,7 @@ def main():
     cap = 1024 if args.config == 4 else 64
 
     ctx = ds.Context(0, g, w)
+    tuned = autotune.apply_cached(ctx.handle, batch, 0)   # the autotuner's launch settings for this workload
     copies = []
     for _ in range(args.copies):
         ev = ds.DeviceEvents(batch)
@@ -253,7 +260,8 @@ def main():
                vs_baseline=None, dtype="f64+f32", data="synthetic",
                config=dict(workload=WORKLOADS[args.config], events_per_step=E, seeds=batch.n_seeds,
                            hits=batch.n_hits, launch="ds_process: one fused persistent launch, hipGraph replay",
-                           rotated_copies=args.copies),
+                           rotated_copies=args.copies, launch_settings=launch_settings(ds, ctx.handle),
+                           autotuned=tuned is not None),
                roofline=roofline, vertex=vertex_info, flags=flags, kernel_source=src_hash)
 
     if not args.no_plain:
@@ -274,6 +282,7 @@ def main():
         # the same batch under Dv1 (triplet search, Y sectors), same launch
         g1 = dict(g, algorithm=1)
         ctx1 = ds.Context(0, g1, w)
+        tuned1 = autotune.apply_cached(ctx1.handle, batch, 1)
         for k in range(args.warmup):
             ev, tr, vt = copies[k % len(copies)]
             ds.ds_process(ctx1.handle, ev, tr, vt, mode, score_max=score_max, stream=stream)
@@ -297,7 +306,8 @@ def main():
                           traffic=stored_traffic("k_track_fused_dv1", src_hash),
                           tracks=int(np.sum(nh1 > 0)), vertices=nv1,
                           flags=int(tr.flags.item()) | int(vt.flags.item()),
-                          launch="ds_process, algorithm 1: one fused persistent launch, hipGraph replay")
+                          launch="ds_process, algorithm 1: one fused persistent launch, hipGraph replay",
+                          launch_settings=launch_settings(ds, ctx1.handle), autotuned=tuned1 is not None)
         ctx1.close()
     if not args.no_copy_ceiling:
         cc = copy_ceiling_gbs(torch)

@@ -1,10 +1,13 @@
-"""Launch autotuner for the tracking and vertexing kernels.
+"""Launch autotuner of the fused step (ds_process: tracking, ghost-killer and
+vertexing in one persistent launch, replayed from a hipGraph).
 
-Sweeps workgroup size, persistent workgroups per compute unit and (tracking
-only) the number of hit bins per layer on a resident device batch, timing each
-point with HIP events on the launch stream (median of `reps` launches), and
-caches the winner per (device, workload signature) in a JSON file.  The
-results are bitwise independent of these settings; only speed changes.
+Sweeps workgroup size, persistent workgroups per compute unit, hit bins per
+layer and the event order (input order or largest first) on a resident device
+batch, timing each point with HIP events on the launch stream (median of
+`reps` graph replays), and caches the winner per (device, algorithm, workload
+signature) in a JSON file that ships with the package.  Results are bitwise
+independent of these settings (tested); only speed changes.  A point whose
+LDS does not fit is refused by the library (DS_E_CAPACITY) and skipped.
 """
 from __future__ import annotations
 
@@ -13,7 +16,6 @@ import itertools
 import json
 import math
 import os
-import sys
 import time
 from typing import Dict, Iterable, List, Optional, Tuple
 
@@ -23,8 +25,8 @@ from . import ds
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
-TRACK_SPACE = dict(block=(64, 128, 256, 512), wg_per_cu=(1, 2, 4, 6, 8), bins=(128, 256, 512, 1024))
-VERTEX_SPACE = dict(block=(64, 128, 256, 512), wg_per_cu=(1, 2, 4, 8))
+SPACE = dict(block=(128, 256, 512), wg_per_cu=(1, 2, 3, 4, 6), bins=(256, 512, 1024),
+             order=(ds.DS_ORDER_INPUT, ds.DS_ORDER_LARGEST_FIRST))
 
 
 def signature(batch) -> str:
@@ -41,8 +43,13 @@ def device_name() -> str:
     return f"{p.name}-{getattr(p, 'gcnArchName', 'gfx')}"
 
 
+def cache_key(batch, algorithm: int) -> str:
+    return f"{device_name()}|alg{int(algorithm)}|{signature(batch)}"
+
+
 def _time(fn, stream, reps: int) -> float:
     import torch
+    fn()
     fn()
     torch.cuda.synchronize()
     ts = []
@@ -57,113 +64,112 @@ def _time(fn, stream, reps: int) -> float:
     return float(np.median(ts))
 
 
-def sweep_track(ctx, ev, tr, points: Iterable[Tuple[int, int, int]], fuse: int = 1, reps: int = 5,
-                stream=None) -> List[Dict]:
+def set_point(ctx, pt: Dict) -> None:
+    ds.ds_set_launch(ctx, 0, pt["block"], pt["wg_per_cu"], pt["bins"])
+    ds.ds_set_event_order(ctx, pt["order"])
+
+
+def sweep_process(ctx, ev, tr, vt, score_max: float, points: Iterable[Tuple[int, int, int, int]], reps: int = 5,
+                  stream=None) -> List[Dict]:
+    """Times ds_process (graph mode) at every (block, wg_per_cu, bins, order) point."""
     import torch
     stream = stream or torch.cuda.current_stream()
     out = []
-    for block, wpc, bins in points:
+    for block, wpc, bins, order in points:
+        pt = dict(block=block, wg_per_cu=wpc, bins=bins, order=order)
         if (4 * bins) % block:
             continue
         try:
-            ds.ds_set_launch(ctx, 0, block, wpc, bins)
-            ms = _time(lambda: ds.ds_find_tracks(ctx, ev, tr, ds.DS_MODE_PERSISTENT, fuse, stream), stream, reps)
+            set_point(ctx, pt)
+            ms = _time(lambda: ds.ds_process(ctx, ev, tr, vt, ds.DS_MODE_GRAPH, score_max=score_max,
+                                             stream=stream), stream, reps)
         except ds.DsError as e:
-            out.append(dict(block=block, wg_per_cu=wpc, bins=bins, ms=None, error=str(e)))
+            out.append(dict(pt, ms=None, error=str(e)))
             continue
-        out.append(dict(block=block, wg_per_cu=wpc, bins=bins, ms=ms))
-    return out
-
-
-def sweep_vertex(ctx, ev, tr, vt, score_max: float, points: Iterable[Tuple[int, int]], reps: int = 5,
-                 stream=None) -> List[Dict]:
-    import torch
-    stream = stream or torch.cuda.current_stream()
-    out = []
-    for block, wpc in points:
-        try:
-            ds.ds_set_launch(ctx, 1, block, wpc, 0)
-            ms = _time(lambda: ds.ds_vertex(ctx, ev, tr, score_max, vt, ds.DS_MODE_PERSISTENT, stream), stream,
-                       reps)
-        except ds.DsError as e:
-            out.append(dict(block=block, wg_per_cu=wpc, ms=None, error=str(e)))
-            continue
-        out.append(dict(block=block, wg_per_cu=wpc, ms=ms))
+        out.append(dict(pt, ms=ms))
     return out
 
 
 def load_cache(path: str = CACHE) -> Dict:
     if os.path.exists(path):
         try:
-            return json.load(open(path))
-        except Exception:
+            with open(path) as f:
+                return json.load(f)
+        except (OSError, ValueError):
             return {}
     return {}
 
 
-def apply_cached(ctx, batch, path: str = CACHE) -> Optional[Dict]:
-    """Set the cached launch settings for this device and workload, if any."""
+def apply_cached(ctx, batch, algorithm: int = 0, path: str = CACHE) -> Optional[Dict]:
+    """Set the cached launch settings for this device, algorithm and workload;
+    returns the entry (None: not tuned, the library defaults stay)."""
     try:
-        key = f"{device_name()}|{signature(batch)}"
+        key = cache_key(batch, algorithm)
     except Exception:
         return None
     entry = load_cache(path).get(key)
     if entry:
-        t, v = entry["track"], entry["vertex"]
-        ds.ds_set_launch(ctx, 0, t["block"], t["wg_per_cu"], t["bins"])
-        ds.ds_set_launch(ctx, 1, v["block"], v["wg_per_cu"], 0)
+        set_point(ctx, entry["best"])
     return entry
 
 
-def autotune(ctx, batch, ev, tr, vt, score_max: float, reps: int = 5, path: Optional[str] = CACHE,
-             track_space=TRACK_SPACE, vertex_space=VERTEX_SPACE, log=print) -> Dict:
-    tpts = list(itertools.product(track_space["block"], track_space["wg_per_cu"], track_space["bins"]))
-    tres = sweep_track(ctx, ev, tr, tpts, reps=reps)
-    ok = [r for r in tres if r["ms"] is not None]
-    best_t = min(ok, key=lambda r: r["ms"])
-    ds.ds_set_launch(ctx, 0, best_t["block"], best_t["wg_per_cu"], best_t["bins"])
-    ds.ds_find_tracks(ctx, ev, tr, ds.DS_MODE_PERSISTENT, 1)
-    vpts = list(itertools.product(vertex_space["block"], vertex_space["wg_per_cu"]))
-    vres = sweep_vertex(ctx, ev, tr, vt, score_max, vpts, reps=reps)
-    okv = [r for r in vres if r["ms"] is not None]
-    best_v = min(okv, key=lambda r: r["ms"])
-    ds.ds_set_launch(ctx, 1, best_v["block"], best_v["wg_per_cu"], 0)
-    entry = dict(track=best_t, vertex=best_v, track_sweep=tres, vertex_sweep=vres, when=time.time())
+def autotune(ctx, batch, ev, tr, vt, score_max: float, algorithm: int = 0, reps: int = 5,
+             path: Optional[str] = CACHE, space=SPACE, log=print) -> Dict:
+    import torch
+    stream = torch.cuda.current_stream()
+    pts = list(itertools.product(space["block"], space["wg_per_cu"], space["bins"], space["order"]))
+    res = sweep_process(ctx, ev, tr, vt, score_max, pts, reps=reps, stream=stream)
+    ok = [r for r in res if r["ms"] is not None]
+    best = {k: min(ok, key=lambda r: r["ms"])[k] for k in ("block", "wg_per_cu", "bins", "order")}
+    # confirm the winner against the library default with more repetitions
+    default = dict(block=256, wg_per_cu=3, bins=1024, order=ds.DS_ORDER_INPUT)
+    confirm = {}
+    for name, pt in (("best", best), ("default", default)):
+        set_point(ctx, pt)
+        confirm[name] = _time(lambda: ds.ds_process(ctx, ev, tr, vt, ds.DS_MODE_GRAPH, score_max=score_max,
+                                                    stream=stream), stream, 3 * reps)
+    pick, ms = (best, confirm["best"]) if confirm["best"] < confirm["default"] else (default, confirm["default"])
+    set_point(ctx, pick)
+    entry = dict(best=pick, ms=round(ms, 4), default_ms=round(confirm["default"], 4), n_events=batch.n_events,
+                 when=round(time.time()))
     if log:
-        log(f"autotune: track best {best_t}, vertex best {best_v}")
+        log(f"autotune alg{algorithm} {signature(batch)}: best {pick} {entry['ms']} ms "
+            f"(default {entry['default_ms']} ms)")
     if path:
         cache = load_cache(path)
-        cache[f"{device_name()}|{signature(batch)}"] = dict(track=best_t, vertex=best_v, when=entry["when"])
+        cache[cache_key(batch, algorithm)] = entry
         tmp = path + ".tmp"
-        json.dump(cache, open(tmp, "w"), indent=1)
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
         os.replace(tmp, path)
-    return entry
+    return dict(entry, sweep=res)
 
 
 def main(argv=None):
     from . import synth
     import torch
     ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--config", type=int, nargs="+", default=[1])
+    ap.add_argument("--algorithm", type=int, default=0)
     ap.add_argument("--events", type=int, default=None)
     ap.add_argument("--reps", type=int, default=5)
-    ap.add_argument("--no-save", action="store_true")
+    ap.add_argument("--out", default=CACHE, help="cache file to update")
     args = ap.parse_args(argv)
-    g = synth.default_geometry()
     w = synth.mlp_weights()
-    b = synth.generate(args.config, n_events=args.events)
-    ctx = ds.Context(0, g, w)
-    ev = ds.DeviceEvents(b)
-    tr = ds.DeviceTracks(b.n_seeds, with_cand=False)
-    vt = ds.DeviceVertices(b.n_events, 1024 if args.config == 4 else 64)
-    sm = math.inf if args.config == 4 else g["ghost_threshold"]
-    entry = autotune(ctx.handle, b, ev, tr, vt, sm, reps=args.reps, path=None if args.no_save else CACHE)
-    for r in sorted((r for r in entry["track_sweep"] if r["ms"] is not None), key=lambda r: r["ms"])[:12]:
-        print("track", r)
-    for r in sorted((r for r in entry["vertex_sweep"] if r["ms"] is not None), key=lambda r: r["ms"])[:6]:
-        print("vertex", r)
-    torch.cuda.synchronize()
-    ctx.close()
+    for config in args.config:
+        g = dict(synth.default_geometry(), algorithm=args.algorithm)
+        b = synth.generate(config, n_events=args.events)
+        ctx = ds.Context(0, g, w)
+        ev = ds.DeviceEvents(b)
+        tr = ds.DeviceTracks(b.n_seeds, with_cand=False)
+        vt = ds.DeviceVertices(b.n_events, 1024 if config == 4 else 64)
+        sm = math.inf if config == 4 else g["ghost_threshold"]
+        entry = autotune(ctx.handle, b, ev, tr, vt, sm, algorithm=args.algorithm, reps=args.reps, path=args.out)
+        for r in sorted((r for r in entry["sweep"] if r["ms"] is not None), key=lambda r: r["ms"])[:8]:
+            print(f"config {config} alg {args.algorithm}", r, flush=True)
+        torch.cuda.synchronize()
+        ctx.close()
+        del ev, tr, vt
 
 
 if __name__ == "__main__":

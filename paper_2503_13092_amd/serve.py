@@ -75,6 +75,9 @@ class GpuBackend:
         self.max_seeds = int(max(2 * pool.seeds_per_event.mean() * max_events, self.max_seeds_per_event))
         self.max_hits = int(max(2 * pool.hits_per_event.mean() * max_events, self.max_hits_per_event))
         self.ctx = ds.Context(device, geometry, weights)
+        # the autotuner's launch settings for this pool's workload, when it has some
+        from . import autotune
+        self.tuned = autotune.apply_cached(self.ctx.handle, pool.batch, int(geometry.get("algorithm", 0)))
         pin = lambda a: torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
         self.h_seed = [pin(getattr(b, k)) for k in ("sx", "sy", "stx", "sty", "sqop")]
         self.h_hu = pin(b.hu)
