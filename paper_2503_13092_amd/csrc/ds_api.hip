@@ -19,7 +19,6 @@ namespace {
 
 constexpr int MAX_STREAM_SLOTS = 64;
 constexpr int MAX_GRAPHS = 64;
-constexpr int VTX_PPT = 4;
 constexpr int ITEMS_PER_SEED = 3;
 constexpr int CLONE_BLOCK = 256;
 constexpr size_t LDS_LIMIT = 160 * 1024 - 256;   // gfx950: 160 KiB per workgroup, minus static use
@@ -109,7 +108,7 @@ struct ds_ctx {
     OrderWs order_ws[MAX_STREAM_SLOTS];
     int event_order = DS_ORDER_INPUT;   // persistent launches: DS_ORDER_*
     Launch trk{256, 3, 1024};  // three resident workgroups per CU (168 VGPRs, ~50 KB LDS): one grid wave
-    Launch vtx{64, 2, 0};     // measured best for the 10k-event batch (wavefront-per-event kernel)
+    Launch vtx{256, 4, 0};    // workgroup per event, four resident per CU
     hipStream_t capture = nullptr;
     std::map<std::string, GraphEntry> graphs;
     uint64_t tick = 0;
@@ -134,7 +133,11 @@ size_t track_lds(int hcap, int nb, int nb3, int block, int icap, int tcap)
     return off + (size_t)icap * 8 + (size_t)tcap * 24;
 }
 
-size_t vertex_lds(int tcap, int block) { return ((size_t)tcap * 24 + (size_t)64 * VTX_PPT * 32) * (size_t)(block / 64); }
+// k_vertex: the event's kept tracks, then the survivor ring of the pair loop
+size_t vertex_lds(int tcap, int block)
+{
+    return round16((size_t)tcap * 24) + sizeof(int) * (size_t)(8 * block);
+}
 
 int round_up(int v, int m) { return ((v + m - 1) / m) * m; }
 
@@ -257,7 +260,10 @@ hipError_t launch_track(int block, const ds::TrackArgs &a, const ds::DevGeom &G,
 template <int B>
 hipError_t launch_vertex_b(const ds::VertexArgs &a, const ds::DevGeom &G, int grid, size_t lds, hipStream_t s)
 {
-    hipLaunchKernelGGL((ds::k_vertex<B, VTX_PPT>), dim3(grid), dim3(B), lds, s, a, G);
+    if (a.m_pipi)
+        hipLaunchKernelGGL((ds::k_vertex<B, true>), dim3(grid), dim3(B), lds, s, a, G);
+    else
+        hipLaunchKernelGGL((ds::k_vertex<B, false>), dim3(grid), dim3(B), lds, s, a, G);
     return hipGetLastError();
 }
 
@@ -286,10 +292,14 @@ hipError_t set_kernel_attributes()
         reinterpret_cast<const void *>(&ds::k_track<B, false, true, true, true>)
         DS_TRACK_FNS(64), DS_TRACK_FNS(128), DS_TRACK_FNS(256), DS_TRACK_FNS(512),
 #undef DS_TRACK_FNS
-        reinterpret_cast<const void *>(&ds::k_vertex<64, VTX_PPT>),
-        reinterpret_cast<const void *>(&ds::k_vertex<128, VTX_PPT>),
-        reinterpret_cast<const void *>(&ds::k_vertex<256, VTX_PPT>),
-        reinterpret_cast<const void *>(&ds::k_vertex<512, VTX_PPT>),
+        reinterpret_cast<const void *>(&ds::k_vertex<64, false>),
+        reinterpret_cast<const void *>(&ds::k_vertex<128, false>),
+        reinterpret_cast<const void *>(&ds::k_vertex<256, false>),
+        reinterpret_cast<const void *>(&ds::k_vertex<512, false>),
+        reinterpret_cast<const void *>(&ds::k_vertex<64, true>),
+        reinterpret_cast<const void *>(&ds::k_vertex<128, true>),
+        reinterpret_cast<const void *>(&ds::k_vertex<256, true>),
+        reinterpret_cast<const void *>(&ds::k_vertex<512, true>),
         reinterpret_cast<const void *>(&ds::k_clone<CLONE_BLOCK>)};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_LIMIT);
@@ -428,15 +438,15 @@ ds_status plan_vertex(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, floa
     a.score = trk->score;
     a.nhits = trk->nhits;
     a.score_max = score_max;
-    a.cap = out->cap_per_event;
-    a.count = out->count;
+    a.vcap = out->cap_per_event;
+    a.vcount = out->count;
     a.vi = out->i;
     a.vj = out->j;
     a.vx = out->x;
     a.vy = out->y;
     a.vz = out->z;
     a.vdoca = out->doca;
-    a.overflow = out->overflow;
+    a.voverflow = out->overflow;
     a.flags = out->flags;
     a.counter = counters + 2;
     a.ev_single = -1;

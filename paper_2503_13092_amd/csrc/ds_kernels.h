@@ -156,10 +156,10 @@ struct VertexArgs {
     const float *x, *y, *tx, *ty, *qop, *score;
     const int *nhits;
     float score_max;
-    int cap;
-    int *count, *vi, *vj;
+    int vcap;
+    int *vcount, *vi, *vj;
     float *vx, *vy, *vz, *vdoca;
-    int *overflow, *flags;
+    int *voverflow, *flags;
     int *counter;        // [0] next event, [1] finished workgroups
     int ev_single;
     int tcap;            // LDS capacity for kept tracks
@@ -1176,86 +1176,134 @@ __device__ __forceinline__ void vertex_extras(const DevGeom &G, const float *WLg
                                      float q1, float q2, double s, double t, float4 V, float out[6]);
 
 // Vertexing of one event by the whole workgroup, from the kept tracks in LDS
-// (slot order): pairs (a < b) in row-major chunks of BLOCK, float32
-// prescreen, float64 Newton PCA of the survivors, order-preserving output.
-// XTR: also the masses and trigger-line scores of each vertex (compiled only
-// where they are asked for: their registers would otherwise count against
-// every fused launch).
-template <int BLOCK, bool XTR>
-__device__ __forceinline__ void vertex_event_block(const TrackArgs &a, const DevGeom &G, int e, int s0, int n,
-                                          const float4 *kst, const float *kq, const int *kslot, int *qk, int *qpass,
-                                          float4 *qres, float2 *qst, int *s_wsum)
+// (slot order), pairs (a < b) in row-major order.  Each lane takes VTX_PPT
+// consecutive pairs of a chunk (one unranking, then steps along the row):
+// opposite charge and the float32 straight-line prescreen; the chunk's
+// survivors are appended, in pair order, to a ring of pair codes in LDS (one
+// workgroup scan per chunk).  Whenever a workgroup's worth of survivors is
+// queued (and at the end) they are fitted together, a lane per pair (float64
+// Newton PCA), and the passing ones written in queue order: vertices come out
+// (i, j)-ordered, and the first vcap of them are kept.  ring: VTX_RING(BLOCK)
+// ints.  XTR: also the masses and trigger-line scores of each vertex
+// (compiled only where they are asked for: their registers would otherwise
+// count against every fused launch).
+constexpr int VTX_PPT = 4;
+template <int BLOCK>
+constexpr int vtx_ring() { return 8 * BLOCK; }   // > BLOCK - 1 + VTX_PPT * BLOCK live entries
+
+__device__ __forceinline__ bool pair_prescreen(const DevGeom &G, float4 A, float4 B)
 {
+    const float wx = A.x - B.x, wy = A.y - B.y;
+    const float nx = A.w - B.w, ny = B.z - A.z;
+    const float nz = fmaf(A.z, B.w, -(A.w * B.z));
+    const float wn = fmaf(wx, nx, wy * ny);
+    const float nn = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
+    return (nn < 1e-6f) || (wn * wn < G.prescreen_thr2 * nn);
+}
+
+// Args: TrackArgs (fused step) or VertexArgs (standalone): the vertex outputs
+// vcap, vcount, vi, vj, vx, vy, vz, vdoca, voverflow, the extras' outputs, WL
+// and the seeds' sqop under the same names.
+template <int BLOCK, bool XTR, typename Args>
+__device__ __forceinline__ void vertex_event_block(const Args &a, const DevGeom &G, int e, int s0, int n,
+                                          const float4 *kst, const float *kq, const int *kslot, int *ring,
+                                          int *s_wsum)
+{
+    constexpr int CH = VTX_PPT * BLOCK, RING = vtx_ring<BLOCK>();
+    static_assert((RING & (RING - 1)) == 0, "ring size a power of two");
     const int tid = threadIdx.x;
     const bool curved = (G.fp != 0.0);
     const int npairs = n * (n - 1) / 2;
-    int out_n = 0;
-    for (int chunk = 0; chunk < npairs; chunk += BLOCK) {
-        const int k = chunk + tid;
-        int pa = 0, pb = 0;
-        bool surv = false;
-        if (k < npairs) {
-            unrank_pair(k, n, pa, pb);
-            surv = ((kslot[pa] ^ kslot[pb]) & 1) != 0;
-            if (surv && !curved) {
-                const float4 A = kst[pa], B = kst[pb];
-                const float wx = A.x - B.x, wy = A.y - B.y;
-                const float nx = A.w - B.w, ny = B.z - A.z;
-                const float nz = fmaf(A.z, B.w, -(A.w * B.z));
-                const float wn = fmaf(wx, nx, wy * ny);
-                const float nn = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
-                surv = (nn < 1e-6f) || (wn * wn < G.prescreen_thr2 * nn);
-            }
-        }
-        int tot;
-        const int pos = block_exclusive_scan<BLOCK>(surv ? 1 : 0, s_wsum, &tot);
-        if (surv) qk[pos] = (pa << 16) | pb;
-        lds_barrier();
-        int pass = 0;
-        if (tid < tot) {
-            const int ia = qk[tid] >> 16, ib = qk[tid] & 0xffff;
-            const float4 A = kst[ia], B = kst[ib];
-            const double g1 = -G.fp * (G.gc0 + G.gc1 * ((double)kq[ia] * 1e-3));
-            const double g2 = -G.fp * (G.gc0 + G.gc1 * ((double)kq[ib] * 1e-3));
-            double vx, vy, vz, dd, ps, pt;
-            const bool good = pca64(G, A.x, A.y, A.z, A.w, g1, B.x, B.y, B.z, B.w, g2, vx, vy, vz, dd, ps, pt);
-            pass = (good && (dd < G.doca_max)) ? 1 : 0;
-            qres[tid] = make_float4((float)vx, (float)vy, (float)vz, (float)dd);
-            qst[tid] = make_float2((float)ps, (float)pt);
-        }
-        int tot2;
-        const int opos = block_exclusive_scan<BLOCK>(pass, s_wsum, &tot2);
-        if (pass) {
-            const int m = out_n + opos;
-            if (m < a.vcap) {
-                const size_t o = (size_t)e * (size_t)a.vcap + (size_t)m;
-                const int ia = qk[tid] >> 16, ib = qk[tid] & 0xffff;
-                a.vi[o] = kslot[ia] >> 1;
-                a.vj[o] = kslot[ib] >> 1;
-                const float4 R = qres[tid];
-                a.vx[o] = R.x;
-                a.vy[o] = R.y;
-                a.vz[o] = R.z;
-                a.vdoca[o] = R.w;
-                if constexpr (XTR) {
-                    const float4 TA = kst[ia], TB = kst[ib];
-                    const double g1 = -G.fp * (G.gc0 + G.gc1 * ((double)kq[ia] * 1e-3));
-                    const double g2 = -G.fp * (G.gc0 + G.gc1 * ((double)kq[ib] * 1e-3));
-                    const float2 ST = qst[tid];
-                    float ex[6];
-                    vertex_extras(G, a.WL, TA, TB, g1, g2, a.sqop[s0 + (kslot[ia] >> 1)],
-                                  a.sqop[s0 + (kslot[ib] >> 1)], ST.x, ST.y, R, ex);
-                    a.m_pipi[o] = ex[0];
-                    a.m_ppi[o] = ex[1];
-                    a.line0[o] = ex[2];
-                    a.line1[o] = ex[3];
-                    a.line2[o] = ex[4];
-                    a.line3[o] = ex[5];
+    int out_n = 0, head = 0, qn = 0;   // workgroup-uniform
+    for (int chunk = 0;;) {
+        const bool more = chunk < npairs;
+        if (more) {
+            const int k0 = chunk + VTX_PPT * tid;
+            int code[VTX_PPT];
+            unsigned m = 0;
+            if (k0 < npairs) {
+                int pa, pb;
+                unrank_pair(k0, n, pa, pb);
+                float4 A = kst[pa];
+                int sa = kslot[pa];
+#pragma unroll
+                for (int j = 0; j < VTX_PPT; ++j) {
+                    if (j > 0 && ++pb >= n) {   // next row
+                        ++pa;
+                        pb = pa + 1;
+                        A = kst[pa < n ? pa : 0];
+                        sa = kslot[pa < n ? pa : 0];
+                    }
+                    code[j] = (pa << 16) | pb;
+                    // past the last pair (pb may reach n) nothing is read out of range
+                    const bool valid = k0 + j < npairs;
+                    const int pbs = valid ? pb : 0;
+                    const bool surv = valid && ((sa ^ kslot[pbs]) & 1) != 0 &&
+                                      (curved || pair_prescreen(G, A, kst[pbs]));
+                    m |= surv ? 1u << j : 0u;
                 }
             }
+            int tot;
+            int pos = block_exclusive_scan<BLOCK>(__popc(m), s_wsum, &tot);
+#pragma unroll
+            for (int j = 0; j < VTX_PPT; ++j)
+                if ((m >> j) & 1u) ring[(head + qn + pos++) & (RING - 1)] = code[j];
+            qn += tot;
+            chunk += CH;
         }
-        out_n += tot2;
-        lds_barrier();
+        // fit the queued survivors a workgroup at a time (all of them at the end)
+        while (qn >= BLOCK || (!more && qn > 0)) {
+            lds_barrier();   // the queued codes are visible
+            const int take = min(qn, BLOCK);
+            int pass = 0, ia = 0, ib = 0;
+            float4 R;
+            float2 ST;
+            if (tid < take) {
+                const int c = ring[(head + tid) & (RING - 1)];
+                ia = c >> 16;
+                ib = c & 0xffff;
+                const float4 A = kst[ia], B = kst[ib];
+                const double g1 = -G.fp * (G.gc0 + G.gc1 * ((double)kq[ia] * 1e-3));
+                const double g2 = -G.fp * (G.gc0 + G.gc1 * ((double)kq[ib] * 1e-3));
+                double vx, vy, vz, dd, ps, pt;
+                const bool good = pca64(G, A.x, A.y, A.z, A.w, g1, B.x, B.y, B.z, B.w, g2, vx, vy, vz, dd, ps, pt);
+                pass = (good && (dd < G.doca_max)) ? 1 : 0;
+                R = make_float4((float)vx, (float)vy, (float)vz, (float)dd);
+                ST = make_float2((float)ps, (float)pt);
+            }
+            int tot2;
+            const int opos = block_exclusive_scan<BLOCK>(pass, s_wsum, &tot2);
+            if (pass) {
+                const int m2 = out_n + opos;
+                if (m2 < a.vcap) {
+                    const size_t o = (size_t)e * (size_t)a.vcap + (size_t)m2;
+                    a.vi[o] = kslot[ia] >> 1;
+                    a.vj[o] = kslot[ib] >> 1;
+                    a.vx[o] = R.x;
+                    a.vy[o] = R.y;
+                    a.vz[o] = R.z;
+                    a.vdoca[o] = R.w;
+                    if constexpr (XTR) {
+                        const float4 TA = kst[ia], TB = kst[ib];
+                        const double g1 = -G.fp * (G.gc0 + G.gc1 * ((double)kq[ia] * 1e-3));
+                        const double g2 = -G.fp * (G.gc0 + G.gc1 * ((double)kq[ib] * 1e-3));
+                        float ex[6];
+                        vertex_extras(G, a.WL, TA, TB, g1, g2, a.sqop[s0 + (kslot[ia] >> 1)],
+                                      a.sqop[s0 + (kslot[ib] >> 1)], ST.x, ST.y, R, ex);
+                        a.m_pipi[o] = ex[0];
+                        a.m_ppi[o] = ex[1];
+                        a.line0[o] = ex[2];
+                        a.line1[o] = ex[3];
+                        a.line2[o] = ex[4];
+                        a.line3[o] = ex[5];
+                    }
+                }
+            }
+            out_n += tot2;
+            head += take;
+            qn -= take;
+        }
+        if (!more) break;
     }
     if (tid == 0) {
         a.vcount[e] = out_n < a.vcap ? out_n : a.vcap;
@@ -1308,14 +1356,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2
     off = (off + (size_t)a0.icap * 4 + 15) & ~(size_t)15;
     unsigned long long *it_hits = reinterpret_cast<unsigned long long *>(smem + off);
     off += (size_t)a0.icap * 8;
-    // fused vertexing: kept tracks of the event, and a pair queue aliasing the item buffers
+    // fused vertexing: kept tracks of the event (its survivor ring aliases the seed constants)
     float4 *kst = reinterpret_cast<float4 *>(smem + off);
     float *kq = reinterpret_cast<float *>(smem + off + (size_t)a0.tcap * 16);
     int *kslot = reinterpret_cast<int *>(smem + off + (size_t)a0.tcap * 20);
-    int *qk = reinterpret_cast<int *>(it_desc);
-    int *qpass = qk + BLOCK;
-    float4 *qres = reinterpret_cast<float4 *>(it_hits);
-    float2 *qst = reinterpret_cast<float2 *>(it_hits + 2 * BLOCK);
     __shared__ int s_nx[8];   // next event and its offsets (fetch_event)
     __shared__ int s_bad, s_nacc, s_nitems, s_nkept;
     __shared__ int s_long;   // Dv1: a seed of the chunk has more than 128 UTbX hits
@@ -1730,7 +1774,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2
         }
         if (VTX) {
             const TrackKernArgs &Kv = kernel_args<TrackKernArgs>();
-            vertex_event_block<BLOCK, XTR>(Kv.a, Kv.G, e, s0, s_nkept, kst, kq, kslot, qk, qpass, qres, qst, s_wsum);
+            vertex_event_block<BLOCK, XTR>(Kv.a, Kv.G, e, s0, s_nkept, kst, kq, kslot, reinterpret_cast<int *>(s_c),
+                                           s_wsum);
         }
     }
     const TrackArgs &a = kernel_args<TrackKernArgs>().a;
@@ -2071,186 +2116,71 @@ __device__ __forceinline__ int wave_exclusive_scan(int v, int *total)
 // chunks of 64*PPT, a float32 straight-line prescreen, float64 Newton PCA of
 // the survivors, and an order-preserving compaction, so vertices come out in
 // (i, j) order.
-template <int BLOCK, int PPT>
+// Standalone vertexing (ds_vertex): a workgroup per event (work-stolen); the
+// event's kept tracks (nhits > 0, score < score_max) are compacted into LDS in
+// slot order, then the pairs go through vertex_event_block, the routine of the
+// fused step.  LDS: kept tracks (24 B each, tcap of them) and the survivor ring.
+template <int BLOCK, bool XTR>
 __global__ __launch_bounds__(BLOCK) void k_vertex(VertexArgs a, DevGeom G)
 {
-    constexpr int CH = 64 * PPT;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const size_t wave_bytes = (size_t)a.tcap * 24 + (size_t)CH * 32;
-    unsigned char *wb = smem + (size_t)wid * wave_bytes;
-    float4 *st = reinterpret_cast<float4 *>(wb);                                   // x, y, tx, ty
-    float *sq = reinterpret_cast<float *>(wb + (size_t)a.tcap * 16);               // track q/p
-    int *sslot = reinterpret_cast<int *>(wb + (size_t)a.tcap * 20);                // slot << 1 | positive
-    int *qk = reinterpret_cast<int *>(wb + (size_t)a.tcap * 24);                   // survivors a << 16 | b
-    float4 *qres = reinterpret_cast<float4 *>(wb + (size_t)a.tcap * 24 + CH * 4);  // vx, vy, vz, doca
-    int *qpass = reinterpret_cast<int *>(wb + (size_t)a.tcap * 24 + CH * 20);
-    float2 *qst = reinterpret_cast<float2 *>(wb + (size_t)a.tcap * 24 + CH * 24);  // PCA offsets s, t
-    const bool curved = (G.fp != 0.0);
-    const bool extras = a.m_pipi != nullptr;
-    const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-
+    float4 *kst = reinterpret_cast<float4 *>(smem);
+    float *kq = reinterpret_cast<float *>(smem + (size_t)a.tcap * 16);
+    int *kslot = reinterpret_cast<int *>(smem + (size_t)a.tcap * 20);
+    int *ring = reinterpret_cast<int *>(smem + (((size_t)a.tcap * 24 + 15) & ~(size_t)15));
+    __shared__ int s_e;
+    __shared__ int s_wsum[BLOCK / 64];
+    const int tid = threadIdx.x;
     for (int iter = 0;; ++iter) {
-        int e = 0;
-        if (lane == 0) {
+        if (tid == 0) {
             if (a.ev_single >= 0)
-                e = (iter == 0 && wid == 0) ? a.ev_single : a.n_events;
+                s_e = iter == 0 ? a.ev_single : a.n_events;
             else
-                e = atomicAdd(&a.counter[0], 1);
+                s_e = atomicAdd(&a.counter[0], 1);
         }
-        e = __shfl(e, 0, 64);
+        lds_barrier();
+        const int e = s_e;
+        lds_barrier();   // s_e read by every wave before it is rewritten
         if (e >= a.n_events) break;
         const int s0 = a.seed_off[e], s1 = a.seed_off[e + 1];
         const bool ok = (0 <= s0) && (s0 <= s1) && (s1 <= a.n_seeds);
         if (!ok || s1 - s0 > a.tcap || s1 - s0 > a.max_seeds) {
-            if (lane == 0) {
+            if (tid == 0) {
                 atomicOr(a.flags, ok ? F_CAPACITY : F_BAD_OFFSETS);
-                a.count[e] = 0;
+                a.vcount[e] = 0;
             }
             continue;
         }
-        // kept tracks, compacted in slot order; four rounds of 64 seeds share
-        // one round trip for the selection and one for the states
+        // kept tracks, compacted in slot order (slot << 1 | positive seed charge)
         int n = 0;
-        constexpr int R = 4;
-        for (int base = s0; base < s1; base += 64 * R) {
-            bool kept[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int i = base + 64 * r + lane;
-                kept[r] = (i < s1) && (a.nhits[i] > 0) && (a.score[i] < a.score_max);
-            }
-            float4 v[R];
-            float qv[R];
-            int pos[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int i = base + 64 * r + lane;
-                if (kept[r]) {
-                    v[r] = make_float4(a.x[i], a.y[i], a.tx[i], a.ty[i]);
-                    qv[r] = a.qop[i];
-                    pos[r] = a.sqop[i] > 0.0f ? 1 : 0;
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const unsigned long long m = __ballot(kept[r]);
-                if (kept[r]) {
-                    const int k = n + __popcll(m & lt_mask);
-                    st[k] = v[r];
-                    sq[k] = qv[r];
-                    sslot[k] = ((base + 64 * r + lane - s0) << 1) | pos[r];
-                }
-                n += __popcll(m);
-            }
-        }
-        wave_sync();
-        const int npairs = n * (n - 1) / 2;
-        int out_n = 0;
-        for (int chunk = 0; chunk < npairs; chunk += CH) {
-            // stage 1: float32 prescreen of PPT consecutive pairs per lane
-            const int k0 = chunk + lane * PPT;
-            int pa = 0, pb = 0;
-            if (k0 < npairs) unrank_pair(k0, n, pa, pb);
-            int pairs[PPT];
-            int bits = 0;
-#pragma unroll
-            for (int r = 0; r < PPT; ++r) {
-                pairs[r] = (pa << 16) | pb;
-                if (k0 + r < npairs) {
-                    const int sa = sslot[pa], sb = sslot[pb];
-                    bool surv = ((sa ^ sb) & 1) != 0;
-                    if (surv && !curved) {
-                        const float4 A = st[pa], B = st[pb];
-                        const float wx = A.x - B.x, wy = A.y - B.y;
-                        const float nx = A.w - B.w, ny = B.z - A.z;
-                        const float nz = fmaf(A.z, B.w, -(A.w * B.z));
-                        const float wn = fmaf(wx, nx, wy * ny);
-                        const float nn = fmaf(nx, nx, fmaf(ny, ny, nz * nz));
-                        surv = (nn < 1e-6f) || (wn * wn < G.prescreen_thr2 * nn);
-                    }
-                    bits |= (surv ? 1 : 0) << r;
-                    ++pb;
-                    if (pb == n) {
-                        ++pa;
-                        pb = pa + 1;
-                    }
-                }
+        for (int base = s0; base < s1; base += BLOCK) {
+            const int i = base + tid;
+            const bool kept = (i < s1) && (a.nhits[i] > 0) && (a.score[i] < a.score_max);
+            float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            float qv = 0.0f;
+            int pos_q = 0;
+            if (kept) {
+                v = make_float4(a.x[i], a.y[i], a.tx[i], a.ty[i]);
+                qv = a.qop[i];
+                pos_q = a.sqop[i] > 0.0f ? 1 : 0;
             }
             int tot;
-            int pos = wave_exclusive_scan(__popc(bits), &tot);
-#pragma unroll
-            for (int r = 0; r < PPT; ++r)
-                if ((bits >> r) & 1) qk[pos++] = pairs[r];
-            wave_sync();
-            // stage 2: float64 Newton refinement of the survivors
-            for (int q = lane; q < tot; q += 64) {
-                const int ia = qk[q] >> 16, ib = qk[q] & 0xffff;
-                const float4 A = st[ia], B = st[ib];
-                const double g1 = -G.fp * (G.gc0 + G.gc1 * ((double)sq[ia] * 1e-3));
-                const double g2 = -G.fp * (G.gc0 + G.gc1 * ((double)sq[ib] * 1e-3));
-                double vx, vy, vz, dd, ps, pt;
-                const bool good = pca64(G, A.x, A.y, A.z, A.w, g1, B.x, B.y, B.z, B.w, g2, vx, vy, vz, dd, ps, pt);
-                qpass[q] = (good && (dd < G.doca_max)) ? 1 : 0;
-                qres[q] = make_float4((float)vx, (float)vy, (float)vz, (float)dd);
-                qst[q] = make_float2((float)ps, (float)pt);
+            const int pos = block_exclusive_scan<BLOCK>(kept ? 1 : 0, s_wsum, &tot);
+            if (kept) {
+                kst[n + pos] = v;
+                kq[n + pos] = qv;
+                kslot[n + pos] = ((i - s0) << 1) | pos_q;
             }
-            wave_sync();
-            // stage 3: order-preserving compaction of the passing pairs
-            int cnt = 0;
-#pragma unroll
-            for (int r = 0; r < PPT; ++r) {
-                const int q = lane * PPT + r;
-                cnt += (q < tot) ? qpass[q] : 0;
-            }
-            int tot2;
-            int opos = wave_exclusive_scan(cnt, &tot2);
-#pragma unroll
-            for (int r = 0; r < PPT; ++r) {
-                const int q = lane * PPT + r;
-                if (q < tot && qpass[q]) {
-                    const int m = out_n + opos++;
-                    if (m < a.cap) {
-                        const size_t o = (size_t)e * (size_t)a.cap + (size_t)m;
-                        const int ia = qk[q] >> 16, ib = qk[q] & 0xffff;
-                        a.vi[o] = sslot[ia] >> 1;
-                        a.vj[o] = sslot[ib] >> 1;
-                        const float4 R = qres[q];
-                        a.vx[o] = R.x;
-                        a.vy[o] = R.y;
-                        a.vz[o] = R.z;
-                        a.vdoca[o] = R.w;
-                        if (extras) {
-                            const float4 TA = st[ia], TB = st[ib];
-                            const double g1 = -G.fp * (G.gc0 + G.gc1 * ((double)sq[ia] * 1e-3));
-                            const double g2 = -G.fp * (G.gc0 + G.gc1 * ((double)sq[ib] * 1e-3));
-                            const float2 ST = qst[q];
-                            float ex[6];
-                            vertex_extras(G, a.WL, TA, TB, g1, g2, a.sqop[a.seed_off[e] + (sslot[ia] >> 1)],
-                                          a.sqop[a.seed_off[e] + (sslot[ib] >> 1)], ST.x, ST.y, R, ex);
-                            a.m_pipi[o] = ex[0];
-                            a.m_ppi[o] = ex[1];
-                            a.line0[o] = ex[2];
-                            a.line1[o] = ex[3];
-                            a.line2[o] = ex[4];
-                            a.line3[o] = ex[5];
-                        }
-                    }
-                }
-            }
-            out_n += tot2;
-            wave_sync();
+            n += tot;
         }
-        if (lane == 0) {
-            a.count[e] = out_n < a.cap ? out_n : a.cap;
-            if (out_n > a.cap) atomicAdd(a.overflow, out_n - a.cap);
-        }
-        wave_sync();
+        lds_barrier();   // the kept tracks are visible
+        vertex_event_block<BLOCK, XTR>(a, G, e, s0, n, kst, kq, kslot, ring, s_wsum);
+        lds_barrier();   // the event's LDS is free again
     }
-    if (a.ev_single < 0 && lane == 0) {
+    if (a.ev_single < 0 && tid == 0) {
         __threadfence();
         const int done = atomicAdd(&a.counter[1], 1);
-        if (done == (int)gridDim.x * (BLOCK / 64) - 1) {
+        if (done == (int)gridDim.x - 1) {
             atomicExch(&a.counter[0], 0);
             atomicExch(&a.counter[1], 0);
             __threadfence();
