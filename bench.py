@@ -24,6 +24,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+FLOPS_PER_PAIR = 250.0   # straight-line start + 3 Newton steps of one opposite-charge pair, float64
 METRIC = "events/s/GPU (tracking+vertexing) and p99 event latency at fixed rate vs plain"
 WORKLOADS = {
     1: "throughput batch: 10000 events x 150 seeds (40% true), 600 UT hits/layer, FP32 SoA",
@@ -51,6 +53,15 @@ def vertex_bytes(batch, kept: int, n_vertices: int) -> float:  # the separate ve
     the state (x, y, tx, ty, q/p) and charge of kept tracks, 24 B per vertex
     and a count per event."""
     return 8.0 * batch.n_seeds + 24.0 * kept + 24.0 * n_vertices + 8.0 * batch.n_events
+
+
+def opposite_charge_pairs(batch, nhits, score, score_max) -> int:
+    """Pairs of kept tracks with opposite seed charge, summed over events."""
+    ev = np.repeat(np.arange(batch.n_events), np.diff(batch.seed_off))
+    kept = (nhits > 0) & (score < score_max)
+    pos = np.bincount(ev, weights=(kept & (batch.sqop > 0)).astype(np.float64), minlength=batch.n_events)
+    neg = np.bincount(ev, weights=(kept & ~(batch.sqop > 0)).astype(np.float64), minlength=batch.n_events)
+    return int(np.sum(pos * neg))
 
 
 def stored_traffic(kernel: str, src_hash: str):
@@ -109,7 +120,8 @@ def cpu_baseline(batch, g, w):
 def launch_settings(ds, ctx):
     block, wpc, bins = ds.ds_get_launch(ctx, 0)
     return dict(block=block, wg_per_cu=wpc, bins=bins,
-                order="largest_first" if ds.ds_get_event_order(ctx) == ds.DS_ORDER_LARGEST_FIRST else "input")
+                order="largest_first" if ds.ds_get_event_order(ctx) == ds.DS_ORDER_LARGEST_FIRST else "input",
+                step="one fused launch" if ds.ds_get_step_fusion(ctx) else "tracking launch, then vertexing launch")
 
 
 def copy_ceiling_gbs(torch, nbytes=2 << 30, reps=10):
@@ -245,21 +257,39 @@ def main():
     src_hash = kernel_source_hash()
     vb = vertex_bytes(batch, kept, n_vtx)
     bpe = track_bytes_per_event(batch)
-    step_bytes = bpe * E + 24.0 * n_vtx + 4.0 * E
-    achieved = step_bytes / (fused_ms * 1e-3) / 1e9
-    traffic = stored_traffic("k_track_fused", src_hash)
+    fused = bool(ds.ds_get_step_fusion(ctx.handle))
+    if fused:
+        # the step is the fused launch (plus, in largest-first order, two small sorting launches)
+        step_bytes = bpe * E + 24.0 * n_vtx + 4.0 * E
+        kms, kname, kkey = fused_ms, ("k_track: hit staging, search, fit, ghost-killer MLP and vertexing fused"
+                                      + (", after the two event-order launches" if launch_settings(ds, ctx.handle)[
+                                          "order"] == "largest_first" else "")), "k_track_fused"
+    else:
+        # two launches: the dominant one is tracking (the vertexing launch has its own flop roofline below)
+        step_bytes = bpe * E
+        kms, kname, kkey = trk_ms, "k_track: hit staging, search, fit and ghost-killer MLP", "k_track"
+    achieved = step_bytes / (kms * 1e-3) / 1e9
+    traffic = stored_traffic(kkey, src_hash) if args.config == 1 else None
     roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 5), traffic=traffic,
-                    kernel="k_track<256,false,true,false,false>: hit staging, search, fit, ghost-killer MLP and vertexing fused",
-                    kernel_ms=round(fused_ms, 4), algorithmic_bytes_per_launch=round(step_bytes))
-    vertex_info = dict(kept_tracks=kept, vertices=n_vtx, unfused_track_ms=round(trk_ms, 4),
-                       unfused_vertex_ms=round(vtx_ms, 4), unfused_vertex_algorithmic_bytes=round(vb))
+                    frac=round(achieved / HBM_PEAK_GBS, 5), traffic=traffic, kernel=kname,
+                    kernel_ms=round(kms, 4), algorithmic_bytes_per_launch=round(step_bytes))
+    opp = opposite_charge_pairs(batch, nh, sc, score_max)
+    vflops = FLOPS_PER_PAIR * opp
+    vertex_info = dict(kept_tracks=kept, vertices=n_vtx, opposite_charge_pairs=opp, unfused_track_ms=round(trk_ms, 4),
+                       unfused_vertex_ms=round(vtx_ms, 4), unfused_vertex_algorithmic_bytes=round(vb),
+                       roofline=dict(bound="alu", unit="TFLOP/s", kernel="k_vertex (ds_vertex)",
+                                     algorithmic_flops_per_launch=round(vflops),
+                                     achieved=round(vflops / (vtx_ms * 1e-3) / 1e12, 3),
+                                     peak=FP64_VECTOR_PEAK_TFLOPS,
+                                     frac=round(vflops / (vtx_ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS, 5),
+                                     note="opposite-charge pairs x 250 float64 flops (start + 3 Newton steps); "
+                                          "the float32 prescreen leaves most pairs unfitted"))
 
     out = dict(metric=METRIC, value=round(value, 1), unit="events/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(ms_per_step, 4), higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="f64+f32", data="synthetic",
                config=dict(workload=WORKLOADS[args.config], events_per_step=E, seeds=batch.n_seeds,
-                           hits=batch.n_hits, launch="ds_process: one fused persistent launch, hipGraph replay",
+                           hits=batch.n_hits, launch="ds_process: persistent launches replayed from a hipGraph",
                            rotated_copies=args.copies, launch_settings=launch_settings(ds, ctx.handle),
                            autotuned=tuned is not None),
                roofline=roofline, vertex=vertex_info, flags=flags, kernel_source=src_hash)

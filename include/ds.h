@@ -281,9 +281,10 @@ ds_status ds_vertex(ds_ctx *ctx, const ds_events *ev, const ds_tracks *trk, floa
                     const ds_vertices *out, int mode, void *hip_stream);
 
 /* The whole step: ds_find_tracks (fused MLP) then ds_vertex with
- * score_max = ghost_threshold (or `score_max` if it is not NaN); with
- * geometry clone_kill set: ds_find_tracks, ds_kill_clones, ds_ghost_kill,
- * ds_vertex.  In DS_MODE_GRAPH all launches are one cached hipGraph. */
+ * score_max = ghost_threshold (or `score_max` if it is not NaN), as one fused
+ * launch or as the two (ds_set_step_fusion); with geometry clone_kill set:
+ * ds_find_tracks, ds_kill_clones, ds_ghost_kill, ds_vertex.  In
+ * DS_MODE_GRAPH all launches are one cached hipGraph. */
 ds_status ds_process(ds_ctx *ctx, const ds_events *ev, const ds_tracks *trk, float score_max,
                      const ds_vertices *out, int mode, void *hip_stream);
 
@@ -332,6 +333,18 @@ enum {
  */
 ds_status ds_set_event_order(ds_ctx *ctx, int order);
 ds_status ds_get_event_order(ds_ctx *ctx, int *order);
+
+/*
+ * Set / read how ds_process and ds_process_static run the step (without
+ * clone killing) in DS_MODE_PERSISTENT and DS_MODE_GRAPH: fused = 1 (the
+ * default) runs tracking, ghost-killer and vertexing in one launch, the kept
+ * tracks of an event never leaving LDS; fused = 0 runs ds_find_tracks (with
+ * the ghost-killer fused) and then ds_vertex, whose kernel holds fewer
+ * registers and more events per compute unit, which pays where pairs
+ * dominate.  Results are identical; only speed differs.
+ */
+ds_status ds_set_step_fusion(ds_ctx *ctx, int fused);
+ds_status ds_get_step_fusion(ds_ctx *ctx, int *fused);
 
 /* Human-readable name of a status code (static string). */
 const char *ds_status_str(ds_status s);

@@ -67,16 +67,17 @@ def _time(fn, stream, reps: int) -> float:
 def set_point(ctx, pt: Dict) -> None:
     ds.ds_set_launch(ctx, 0, pt["block"], pt["wg_per_cu"], pt["bins"])
     ds.ds_set_event_order(ctx, pt["order"])
+    ds.ds_set_step_fusion(ctx, pt.get("fused", 1))
 
 
 def sweep_process(ctx, ev, tr, vt, score_max: float, points: Iterable[Tuple[int, int, int, int]], reps: int = 5,
-                  stream=None) -> List[Dict]:
+                  stream=None, fused: int = 1) -> List[Dict]:
     """Times ds_process (graph mode) at every (block, wg_per_cu, bins, order) point."""
     import torch
     stream = stream or torch.cuda.current_stream()
     out = []
     for block, wpc, bins, order in points:
-        pt = dict(block=block, wg_per_cu=wpc, bins=bins, order=order)
+        pt = dict(block=block, wg_per_cu=wpc, bins=bins, order=order, fused=fused)
         if (4 * bins) % block:
             continue
         try:
@@ -121,14 +122,19 @@ def autotune(ctx, batch, ev, tr, vt, score_max: float, algorithm: int = 0, reps:
     res = sweep_process(ctx, ev, tr, vt, score_max, pts, reps=reps, stream=stream)
     ok = [r for r in res if r["ms"] is not None]
     best = {k: min(ok, key=lambda r: r["ms"])[k] for k in ("block", "wg_per_cu", "bins", "order")}
+    best["fused"] = 1
+    # the winner as two launches (tracking, then the standalone vertexing)
+    res += sweep_process(ctx, ev, tr, vt, score_max, [(best["block"], best["wg_per_cu"], best["bins"], best["order"])],
+                         reps=reps, stream=stream, fused=0)
     # confirm the winner against the library default with more repetitions
-    default = dict(block=256, wg_per_cu=3, bins=1024, order=ds.DS_ORDER_INPUT)
+    default = dict(block=256, wg_per_cu=3, bins=1024, order=ds.DS_ORDER_INPUT, fused=1)
     confirm = {}
-    for name, pt in (("best", best), ("default", default)):
+    for name, pt in (("best", best), ("unfused", dict(best, fused=0)), ("default", default)):
         set_point(ctx, pt)
         confirm[name] = _time(lambda: ds.ds_process(ctx, ev, tr, vt, ds.DS_MODE_GRAPH, score_max=score_max,
                                                     stream=stream), stream, 3 * reps)
-    pick, ms = (best, confirm["best"]) if confirm["best"] < confirm["default"] else (default, confirm["default"])
+    cands = [(confirm["best"], best), (confirm["unfused"], dict(best, fused=0)), (confirm["default"], default)]
+    ms, pick = min(cands, key=lambda c: c[0])
     set_point(ctx, pick)
     entry = dict(best=pick, ms=round(ms, 4), default_ms=round(confirm["default"], 4), n_events=batch.n_events,
                  when=round(time.time()))

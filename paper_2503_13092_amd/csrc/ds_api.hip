@@ -107,6 +107,7 @@ struct ds_ctx {
     std::map<void *, int> slots;
     OrderWs order_ws[MAX_STREAM_SLOTS];
     int event_order = DS_ORDER_INPUT;   // persistent launches: DS_ORDER_*
+    int fused_step = 1;                 // ds_process: one fused launch (1) or tracking then vertexing (0)
     Launch trk{256, 3, 1024};  // three resident workgroups per CU (168 VGPRs, ~50 KB LDS): one grid wave
     Launch vtx{256, 4, 0};    // workgroup per event, four resident per CU
     hipStream_t capture = nullptr;
@@ -672,7 +673,7 @@ ds_status process_enqueue(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, 
         st = clone_args(ev, trk, &ca, &clds);
         if (st != DS_OK) return st;
     }
-    if (!ck && mode != DS_MODE_PER_EVENT) {
+    if (!ck && mode != DS_MODE_PER_EVENT && c->fused_step) {
         // one launch: tracking, ghost-killer and vertexing fused per event
         TrackPlan fp;
         st = plan_track(c, ev, trk, 1, counters, &fp, true);
@@ -1097,6 +1098,22 @@ ds_status ds_set_event_order(ds_ctx *c, int order)
     if (!c || (order != DS_ORDER_INPUT && order != DS_ORDER_LARGEST_FIRST)) return DS_E_ARG;
     std::lock_guard<std::mutex> lock(c->mu);
     c->event_order = order;
+    return DS_OK;
+}
+
+ds_status ds_set_step_fusion(ds_ctx *c, int fused)
+{
+    if (!c || (fused != 0 && fused != 1)) return DS_E_ARG;
+    std::lock_guard<std::mutex> lock(c->mu);
+    c->fused_step = fused;
+    return DS_OK;
+}
+
+ds_status ds_get_step_fusion(ds_ctx *c, int *fused)
+{
+    if (!c || !fused) return DS_E_ARG;
+    std::lock_guard<std::mutex> lock(c->mu);
+    *fused = c->fused_step;
     return DS_OK;
 }
 

@@ -26,7 +26,8 @@ DS_STATIC_MAX_EVENTS = 262144
 
 EXPORTED = ("ds_create", "ds_destroy", "ds_load_geometry", "ds_find_tracks", "ds_ghost_kill", "ds_kill_clones",
             "ds_candidate_slots", "ds_score_candidates", "ds_load_lines", "ds_vertex", "ds_process", "ds_process_static", "ds_set_launch",
-            "ds_get_launch", "ds_set_event_order", "ds_get_event_order", "ds_status_str")
+            "ds_get_launch", "ds_set_event_order", "ds_get_event_order", "ds_set_step_fusion",
+            "ds_get_step_fusion", "ds_status_str")
 
 
 class DsGeometry(C.Structure):
@@ -129,6 +130,8 @@ def library() -> C.CDLL:
         lib.ds_get_launch.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
         lib.ds_set_event_order.argtypes = [P, C.c_int]
         lib.ds_get_event_order.argtypes = [P, C.POINTER(C.c_int)]
+        lib.ds_set_step_fusion.argtypes = [P, C.c_int]
+        lib.ds_get_step_fusion.argtypes = [P, C.POINTER(C.c_int)]
         lib.ds_status_str.argtypes = [C.c_int]
         lib.ds_status_str.restype = C.c_char_p
         for name in EXPORTED:
@@ -406,6 +409,16 @@ def ds_set_event_order(ctx, order: int) -> None:
 def ds_get_event_order(ctx) -> int:
     o = C.c_int()
     _check(library().ds_get_event_order(ctx, C.byref(o)), "ds_get_event_order")
+    return o.value
+
+
+def ds_set_step_fusion(ctx, fused: int) -> None:
+    _check(library().ds_set_step_fusion(ctx, int(fused)), "ds_set_step_fusion")
+
+
+def ds_get_step_fusion(ctx) -> int:
+    o = C.c_int()
+    _check(library().ds_get_step_fusion(ctx, C.byref(o)), "ds_get_step_fusion")
     return o.value
 
 
