@@ -29,6 +29,14 @@ these seeded events stand in for them):
 * Hits: true hits at layers downstream of the decay with N(0, 0.05) mm
   smear; noise hits uniform over |x| < 800, |y| < 700 mm; hits shuffled
   within each (event, layer) run, seeds shuffled within each event.
+* Fringe field (geometry ``fringe_polarity`` = +-1; 0, the default, keeps
+  the straight lines above): between the decay point and the UT a daughter
+  follows the eq. 4 parabola x(z) = x0 + tx0 (z - z0) + gamma (z - z0)^2,
+  y linear, with gamma = -MP (c0 + c1 q/p[MeV^-1]) from eq. 3 and z0 the UT
+  midpoint; (x0, tx0) is its state there, and from z0 on it is the straight
+  line of the UT and the kink model.  The slopes drawn at the decay point are
+  the parabola's there, so the generated decay point lies exactly on both
+  daughters' eq. 4 trajectories.  No extra random draws.
 * Y sectors: every hit also carries the 100 mm band of its layer that its
   true y falls in (14 bands over |y| < 700 mm); Dv1's triplet search uses
   them.  They are computed from the generated y, with no extra random draw.
@@ -222,9 +230,23 @@ def _log_uniform(rng, lo, hi, n):
     return np.exp(rng.uniform(math.log(lo), math.log(hi), n))
 
 
+def fringe_gamma(g: Dict, qop) -> np.ndarray:
+    """Eq. 3: the second-order coefficient (mm^-1) of a track's x(z) between
+    the decay point and the UT, q/p in GeV^-1 (converted to MeV^-1)."""
+    return -g["fringe_polarity"] * (g["gamma_c0"] + g["gamma_c1"] * np.asarray(qop) * 1e-3)
+
+
+def _ut_state(g, vx, tx_v, zd, gam):
+    """x and tx at the UT midpoint z0 of the parabola through (vx, zd) with
+    slope tx_v there and second-order coefficient gam."""
+    h = g["z_ref"] - zd
+    return vx + tx_v * h + gam * h * h, tx_v + 2.0 * gam * h
+
+
 def _draw_daughters(rng, g, llp_tx, llp_ty, llp_z, charge, accept_ut=True):
     """Momenta and slopes for daughters of the given parents (one row each),
-    redrawn until inside the acceptance.  Returns p, tx_before, ty."""
+    redrawn until inside the acceptance.  Returns p, tx_before, ty (with a
+    fringe field: the slope at the decay point)."""
     n = len(llp_tx)
     p = np.empty(n)
     tx = np.empty(n)
@@ -240,16 +262,23 @@ def _draw_daughters(rng, g, llp_tx, llp_ty, llp_z, charge, accept_ut=True):
         ty[todo] = llp_ty[todo] + rng.normal(0.0, 0.02, m)
         zd = llp_z[todo]
         vx, vy = llp_tx[todo] * zd, llp_ty[todo] * zd
+        qop = charge[todo] / p[todo]
+        curved = g.get("fringe_polarity", 0.0) != 0.0
+        if curved:   # the UT line of the eq. 4 parabola
+            x0, tx0 = _ut_state(g, vx, tx[todo], zd, fringe_gamma(g, qop))
         ok = np.ones(m, bool)
         if accept_ut:
             for L in range(4):
                 down = zl[L] > zd
-                xL = vx + tx[todo] * (zl[L] - zd)
+                xL = x0 + tx0 * (zl[L] - g["z_ref"]) if curved else vx + tx[todo] * (zl[L] - zd)
                 yL = vy + ty[todo] * (zl[L] - zd)
                 ok &= ~down | ((np.abs(xL) < UT_XMAX) & (np.abs(yL) < UT_YMAX))
-        qop = charge[todo] / p[todo]
-        xm = vx + tx[todo] * (g["z_magnet"] - zd)
-        txa = tx[todo] + g["polarity"] * g["kick"] * qop
+        if curved:
+            xm = x0 + tx0 * (g["z_magnet"] - g["z_ref"])
+            txa = tx0 + g["polarity"] * g["kick"] * qop
+        else:
+            xm = vx + tx[todo] * (g["z_magnet"] - zd)
+            txa = tx[todo] + g["polarity"] * g["kick"] * qop
         xs = xm + txa * (g["z_seed"] - g["z_magnet"])
         ys = vy + ty[todo] * (g["z_seed"] - zd)
         ok &= (np.abs(xs) < SEED_XMAX) & (np.abs(ys) < SEED_YMAX)
@@ -331,6 +360,17 @@ def generate(config=1, n_events: Optional[int] = None, seed: Optional[int] = Non
     T_true = np.concatenate([np.ones(2 * NL, bool), np.zeros(NG, bool)])
     T_llp = np.concatenate([d_par, np.full(NG, -1)])
     NT = len(T_ev)
+    curved = g.get("fringe_polarity", 0.0) != 0.0
+    T_gam = fringe_gamma(g, T_qop) if curved else np.zeros(NT)
+    if curved:
+        # from the UT on, the straight line with the parabola's UT state:
+        # re-anchor it at the decay z so that the code below is unchanged
+        x0, tx0 = _ut_state(g, T_vx, T_txb, T_z, T_gam)
+        T_txb = tx0
+        T_vx = x0 - tx0 * (g["z_ref"] - T_z)
+        T_vx_true = np.concatenate([llp_tx[d_par] * d_z, g_tx * g_z])
+    else:
+        T_vx_true = T_vx
 
     xm = T_vx + T_txb * (g["z_magnet"] - T_z)
     txa = T_txb + g["polarity"] * g["kick"] * T_qop
@@ -403,8 +443,10 @@ def generate(config=1, n_events: Optional[int] = None, seed: Optional[int] = Non
     hit_owner = np.where(all_owner_track >= 0, track_to_seed[np.maximum(all_owner_track, 0)], -1)
     truth = dict(
         seed_true=T_true[sorder], seed_llp=T_llp[sorder], seed_qop=T_qop[sorder],
-        seed_zdecay=T_z[sorder], seed_vx=T_vx[sorder], seed_vy=T_vy[sorder],
-        seed_txb=T_txb[sorder], seed_ty=T_ty[sorder],
+        seed_zdecay=T_z[sorder], seed_vx=T_vx_true[sorder], seed_vy=T_vy[sorder],
+        seed_txb=T_txb[sorder], seed_ty=T_ty[sorder], seed_gamma=T_gam[sorder],
+        # the state at the UT midpoint (x0, y0, tx0 = seed_txb, ty0 = seed_ty)
+        seed_x0=(T_vx + T_txb * (g["z_ref"] - T_z))[sorder], seed_y0=(T_vy + T_ty * (g["z_ref"] - T_z))[sorder],
         hit_owner=hit_owner.astype(np.int64), hit_layer=(all_grp % 4).astype(np.int8),
     )
     if keep_float64:

@@ -387,6 +387,48 @@ def test_largest_first_order_matches_oracle_and_input_order():
         c.close()
 
 
+@pytest.mark.parametrize("fp", [1.0, -1.0])
+def test_curved_daughters_path_matches_oracle(fp):
+    """Daughters generated on eq. 4 parabolas before the UT (eq. 3 gamma,
+    fringe polarity +-1): the fused graph step with every found track
+    vertexed (the straight-line prescreen is off when gamma != 0, so every
+    opposite-charge pair goes through the float64 Newton fit) equals the
+    oracle track by track and vertex by vertex, and LLP daughter pairs are
+    vertexed near their generated decay points."""
+    g = dict(G0, fringe_polarity=fp)
+    b = synth.generate(1, n_events=120, seed=60, geometry=g)
+    c = ds.Context(0, g, W)
+    try:
+        say(f"[curved] fringe polarity {fp}: {b.n_seeds} seeds, {b.n_hits} hits")
+        ev = ds.DeviceEvents(b)
+        tr = ds.DeviceTracks(b.n_seeds)
+        vt = ds.DeviceVertices(b.n_events, 1024)
+        ds.ds_process(c.handle, ev, tr, vt, ds.DS_MODE_GRAPH, score_max=math.inf)
+        torch.cuda.synchronize()
+        gt, gv = tr.to_numpy(), vt.to_numpy()
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+    assert gt["flags"] == 0 and gv["flags"] == 0
+    ref = O.run_path(b, g, W, score_max=math.inf, cap=1024, n_threads=8)
+    tc = parity.compare_tracks(gt, ref["tracks"])
+    found = ref["tracks"]["nhits"] > 0
+    sc = parity.compare_scores(gt["score"], ref["score"], found & (gt["nhits"] == ref["tracks"]["nhits"]))
+    vc = parity.compare_vertices(gv, ref["vertices"], g["doca_max"], parity.excused_slot_set(b, tc, sc))
+    t = b.truth
+    dz = []
+    for e in range(b.n_events):
+        s0 = b.seed_off[e]
+        for m in range(int(gv["count"][e])):
+            k = e * gv["cap"] + m
+            i, j = s0 + gv["i"][k], s0 + gv["j"][k]
+            if t["seed_true"][i] and t["seed_llp"][i] == t["seed_llp"][j]:
+                dz.append(abs(gv["z"][k] - t["seed_zdecay"][i]))
+    say(f"[curved] fringe polarity {fp}: identical {tc['identical']}/{tc['n']}, vertices {vc['n_gpu']}/{vc['n_ref']}, "
+        f"LLP vertices {len(dz)}, median |dz| {np.median(dz):.1f} mm")
+    assert len(dz) >= 500 and np.median(dz) < 60.0
+
+
 def _edge_event(rng, g, xs_ut, n_noise=40):
     """One hand-built event whose true tracks cross the UT near and beyond the
     hit-binning range |u| <= u_max: hits are forward-simulated from states
@@ -526,16 +568,21 @@ def test_every_candidate_scored_matches_oracle():
 
 @pytest.mark.parametrize("algorithm", [0, 1])
 def test_launch_shapes_bitwise_equal(algorithm):
-    """Block size, workgroups per CU and hit bins (the autotuner's knobs)
-    change chunking, scheduling and the bucket layout, never the results."""
+    """Block size, workgroups per CU, hit bins, event order and step fusion
+    (the autotuner's knobs) change chunking, scheduling, the bucket layout
+    and the launches, never the results."""
     g = dict(G0, algorithm=algorithm)
     b = synth.generate(0, n_events=80, seed=23)
     c = ds.Context(0, g, W)
     try:
         outs = []
-        for block, wpc, bins in ((256, 3, 512), (64, 8, 512), (128, 4, 256), (512, 1, 1024), (256, 2, 128)):
-            say(f"[parity] launch shape, algorithm {algorithm}: block {block}, {wpc} per CU, {bins} bins")
+        for block, wpc, bins, order, fused in ((256, 3, 512, 0, 1), (64, 8, 512, 1, 1), (128, 4, 256, 0, 0),
+                                               (512, 1, 1024, 1, 0), (256, 2, 128, 0, 1), (256, 3, 1024, 1, 0)):
+            say(f"[parity] launch shape, algorithm {algorithm}: block {block}, {wpc} per CU, {bins} bins, "
+                f"order {order}, fused {fused}")
             ds.ds_set_launch(c.handle, 0, block, wpc, bins)
+            ds.ds_set_event_order(c.handle, order)
+            ds.ds_set_step_fusion(c.handle, fused)
             ev = ds.DeviceEvents(b)
             tr = ds.DeviceTracks(b.n_seeds)
             vt = ds.DeviceVertices(b.n_events, 256)
