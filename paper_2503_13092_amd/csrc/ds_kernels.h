@@ -260,13 +260,23 @@ __device__ __forceinline__ bool before(const float *hu_s, const uint16_t *hidx_s
     return hidx_s[p] < hidx_s[pk];
 }
 
+// The window's bin bounds in float32: m and W rounded (errors below 1e-4 mm
+// for |m| < 2000 mm) and widened by 1e-3 mm, so the buckets always cover
+// [m - W, m + W] (a superset: membership is decided on |u - m| <= W in float64).
+__device__ __forceinline__ void window_bins(double m, double W, float u0, float inv_bw, int nb, int &b_lo, int &b_hi)
+{
+    const float mf = (float)m, wf = (float)W + 1e-3f;
+    b_lo = bin_of(mf - wf, u0, inv_bw, nb);
+    b_hi = bin_of(mf + wf, u0, inv_bw, nb);
+}
+
 // LDS positions [p_lo, p_hi) of the buckets of `layer` covering [m - W, m + W]
 // (a superset of the window: membership is decided on |u - m| <= W).
 __device__ __forceinline__ void bin_range(const uint16_t *E, int layer, int nb, float u0, float inv_bw, double m, double W,
                                  int &p_lo, int &p_hi)
 {
-    const int b_lo = bin_of((float)(m - W - 1e-3), u0, inv_bw, nb);
-    const int b_hi = bin_of((float)(m + W + 1e-3), u0, inv_bw, nb);
+    int b_lo, b_hi;
+    window_bins(m, W, u0, inv_bw, nb, b_lo, b_hi);
     p_lo = E[layer * nb + b_lo];
     p_hi = E[layer * nb + b_hi + 1];
 }
@@ -620,8 +630,8 @@ __device__ __forceinline__ void sector_span(const SeedConst &sc, int L, int &klo
 __device__ __forceinline__ void sector_bins(const uint16_t *E, const TrackArgs &a, int nsec, int L, int klo, int khi, double m,
                                    double W, int &lo0, int &len0, int &lo1, int &len1)
 {
-    const int b_lo = bin_of((float)(m - W - 1e-3), a.u0, a.inv_bw, a.nbu);
-    const int b_hi = bin_of((float)(m + W + 1e-3), a.u0, a.inv_bw, a.nbu);
+    int b_lo, b_hi;
+    window_bins(m, W, a.u0, a.inv_bw, a.nbu, b_lo, b_hi);
     const int base0 = L * a.nb + min(klo, nsec - 1) * a.nbu, base1 = L * a.nb + min(klo + 1, nsec - 1) * a.nbu;
     const int e0 = E[base0 + b_lo], e1 = E[base0 + b_hi + 1], e2 = E[base1 + b_lo], e3 = E[base1 + b_hi + 1];
     const bool in0 = klo <= khi, in1 = klo + 1 <= khi;
@@ -1043,16 +1053,43 @@ __device__ __forceinline__ BinParams bin_params(const TrackArgs &a)
 // Bucket of a hit: (layer, u bin) for Dv0; (layer, Y sector, u bin) for Dv1,
 // with one last bucket per layer for sector ids outside [0, nsec).
 template <bool DV1>
-__device__ __forceinline__ int hit_bucket(const TrackArgs &a, const BinParams &bp, int nsec, int L, float u, int k)
+__device__ __forceinline__ int hit_bucket(const BinParams &bp, int nsec, int L, float u, int sec)
 {
     const bool l3 = DV1 && L == 3;   // Dv0's layer 3 has the common layout
     const int nbu = l3 ? bp.nbu3 : bp.nbu;
     int b = L * bp.nb + bin_of(u, bp.u0, l3 ? bp.inv_bw3 : bp.inv_bw, nbu);
-    if (DV1) {
-        const int sec = a.hsec[k];
-        b = sec < nsec ? b + sec * nbu : L * bp.nb + nsec * nbu;
-    }
+    if (DV1) b = sec < nsec ? b + sec * nbu : L * bp.nb + nsec * nbu;
     return b;
+}
+
+// The hits of one staging round of a layer (slot j: hit r 64 HPT + lane + 64 j
+// of the run at `base`, n hits): their u and, for Dv1, their Y sector bytes,
+// four to a word, loaded with them (not again at each use).
+template <bool DV1, int HPT>
+__device__ __forceinline__ void load_round(const TrackArgs &a, int base, int n, int r, float u[HPT],
+                                           uint32_t sp[HPT / 4])
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < HPT; ++j) {
+        const int k = r * 64 * HPT + lane + 64 * j;
+        u[j] = (k < n) ? a.hu[base + k] : 0.0f;
+    }
+    if (DV1) {
+#pragma unroll
+        for (int q = 0; q < HPT / 4; ++q) sp[q] = 0u;
+#pragma unroll
+        for (int j = 0; j < HPT; ++j) {
+            const int k = r * 64 * HPT + lane + 64 * j;
+            if (k < n) sp[j >> 2] |= (uint32_t)a.hsec[base + k] << (8 * (j & 3));
+        }
+    }
+}
+
+template <int HPT>
+__device__ __forceinline__ int slot_sector(const uint32_t sp[HPT / 4], int j)
+{
+    return (int)((sp[j >> 2] >> (8 * (j & 3))) & 0xffu);
 }
 
 constexpr int STAGE_HPT = 16;   // hits per lane per staging round
@@ -1086,11 +1123,8 @@ __device__ __forceinline__ bool stage_hits_w(const TrackArgs &a, int nsec, int h
     int L = wave;
     int lo = L < 4 ? hl[L] : 0, n = L < 4 ? (L < 3 ? hl[L + 1] : nh) - hl[L] : 0;
     float u[HPT];
-#pragma unroll
-    for (int j = 0; j < HPT; ++j) {
-        const int k = lane + 64 * j;
-        u[j] = (k < n) ? a.hu[hb + lo + k] : 0.0f;
-    }
+    uint32_t sp[HPT / 4];
+    load_round<DV1, HPT>(a, hb + lo, n, 0, u, sp);
     if (tid == 0) E[0] = 0;
     between();
     const BinParams bp = bin_params(a);
@@ -1099,31 +1133,21 @@ __device__ __forceinline__ bool stage_hits_w(const TrackArgs &a, int nsec, int h
         if (L != wave) {   // a further layer of this wavefront (fewer than four wavefronts)
             lo = hl[L];
             n = (L < 3 ? hl[L + 1] : nh) - lo;
-#pragma unroll
-            for (int j = 0; j < HPT; ++j) {
-                const int k = lane + 64 * j;
-                u[j] = (k < n) ? a.hu[hb + lo + k] : 0.0f;
-            }
+            load_round<DV1, HPT>(a, hb + lo, n, 0, u, sp);
         }
         uint16_t *EL = E + 1 + L * bp.nb;   // EL[b]: count, then end, of bucket (L, b)
         const int nb = (DV1 && L == 3) ? bp.nb3 : bp.nb;
         for (int b = lane; b < nb; b += 64) EL[b] = 0;
         const int rounds = (n + 64 * HPT - 1) / (64 * HPT);
         for (int r = 0; r < rounds; ++r) {
-            if (r > 0) {
-#pragma unroll
-                for (int j = 0; j < HPT; ++j) {
-                    const int k = r * 64 * HPT + lane + 64 * j;
-                    u[j] = (k < n) ? a.hu[hb + lo + k] : 0.0f;
-                }
-            }
+            if (r > 0) load_round<DV1, HPT>(a, hb + lo, n, r, u, sp);
 #pragma unroll
             for (int j = 0; j < HPT; ++j) {
                 if (r * 64 * HPT + 64 * j >= n) break;   // uniform: no lane has slot j
                 const int k = r * 64 * HPT + lane + 64 * j;
                 if (k < n) {
                     if (!isfinite(u[j])) bad = true;
-                    else bkt_add(E, hit_bucket<DV1>(a, bp, nsec, L, u[j], hb + lo + k) + 1);
+                    else bkt_add(E, hit_bucket<DV1>(bp, nsec, L, u[j], slot_sector<HPT>(sp, j)) + 1);
                 }
             }
         }
@@ -1144,19 +1168,13 @@ __device__ __forceinline__ bool stage_hits_w(const TrackArgs &a, int nsec, int h
         }
         // placing pass: EL[b] advances to the end of bucket b
         for (int r = 0; r < rounds; ++r) {
-            if (rounds > 1) {
-#pragma unroll
-                for (int j = 0; j < HPT; ++j) {
-                    const int k = r * 64 * HPT + lane + 64 * j;
-                    u[j] = (k < n) ? a.hu[hb + lo + k] : 0.0f;
-                }
-            }
+            if (rounds > 1) load_round<DV1, HPT>(a, hb + lo, n, r, u, sp);
 #pragma unroll
             for (int j = 0; j < HPT; ++j) {
                 if (r * 64 * HPT + 64 * j >= n) break;
                 const int k = r * 64 * HPT + lane + 64 * j;
                 if (k < n && isfinite(u[j])) {
-                    const int pos = bkt_add(E, hit_bucket<DV1>(a, bp, nsec, L, u[j], hb + lo + k) + 1);
+                    const int pos = bkt_add(E, hit_bucket<DV1>(bp, nsec, L, u[j], slot_sector<HPT>(sp, j)) + 1);
                     hu_s[pos] = u[j];
                     hidx_s[pos] = (uint16_t)k;
                 }
