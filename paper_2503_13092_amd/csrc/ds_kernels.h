@@ -1105,6 +1105,61 @@ __device__ __forceinline__ int bkt_add(uint16_t *E, int i)
     return (int)((atomicAdd(w, 1u << sh) >> sh) & 0xffffu);
 }
 
+// Zero the n 16-bit bounds at EL (one wavefront): 16-byte stores over the
+// aligned middle, single bounds at the two ends.
+__device__ __forceinline__ void zero_bounds(uint16_t *EL, int n)
+{
+    const int lane = threadIdx.x & 63;
+    const int head = (int)((16 - (reinterpret_cast<uintptr_t>(EL) & 15)) & 15) / 2;   // bounds before 16-B alignment
+    const int h = min(head, n);
+    if (lane < h) EL[lane] = 0;
+    const int nv = (n - h) / 8;   // whole 8-bound (16-byte) groups
+    uint4 *V = reinterpret_cast<uint4 *>(EL + h);
+    for (int q = lane; q < nv; q += 64) V[q] = make_uint4(0u, 0u, 0u, 0u);
+    for (int b = h + 8 * nv + lane; b < n; b += 64) EL[b] = 0;
+}
+
+// Exclusive prefix, offset by `carry`, of the n 16-bit counts at EL (one
+// wavefront), two counts per lane per step: a lane reads the pair (b, b + 1)
+// of its 32-bit word, the wavefront sums the pairs (DPP, no LDS traffic) and
+// the lane writes both starts back; eight independent 128-bound pieces per
+// round, then the carries.  EL may start at an odd bound: the first and last
+// bounds outside whole words go on their own.
+__device__ __forceinline__ void scan_bounds(uint16_t *EL, int n, int carry)
+{
+    const int lane = threadIdx.x & 63;
+    int first = 0;
+    if (reinterpret_cast<uintptr_t>(EL) & 2) {   // EL[0] is the high half of a word
+        first = n > 0 ? (int)EL[0] : 0;
+        if (lane == 0 && n > 0) EL[0] = (uint16_t)carry;
+        carry += first;
+        ++EL;
+        --n;
+    }
+    uint32_t *W = reinterpret_cast<uint32_t *>(EL);
+    const int nw = n / 2;
+    for (int w0 = 0; w0 < nw; w0 += 512) {
+        uint32_t pr[8];
+        int v[8], incl[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int w = w0 + 64 * j + lane;
+            pr[j] = w < nw ? W[w] : 0u;
+            v[j] = (int)(pr[j] & 0xffffu) + (int)(pr[j] >> 16);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) incl[j] = wave_inclusive_sum(v[j]);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int w = w0 + 64 * j + lane;
+            const int s0 = carry + incl[j] - v[j], s1 = s0 + (int)(pr[j] & 0xffffu);
+            if (w < nw) W[w] = (uint32_t)s0 | ((uint32_t)s1 << 16);
+            carry += __builtin_amdgcn_readlane(incl[j], 63);
+        }
+    }
+    if ((n & 1) && lane == 0) EL[n - 1] = (uint16_t)carry;   // a last bound in the low half of a word
+}
+
 // Stage one event's hits a wavefront per layer: each wavefront counts its
 // layer's hits into the layer's buckets, scans them (64 buckets per step, DPP
 // sums) and places the hits, with no workgroup barrier until the end: a
@@ -1137,7 +1192,7 @@ __device__ __forceinline__ bool stage_hits_w(const TrackArgs &a, int nsec, int h
         }
         uint16_t *EL = E + 1 + L * bp.nb;   // EL[b]: count, then end, of bucket (L, b)
         const int nb = (DV1 && L == 3) ? bp.nb3 : bp.nb;
-        for (int b = lane; b < nb; b += 64) EL[b] = 0;
+        zero_bounds(EL, nb);
         const int rounds = (n + 64 * HPT - 1) / (64 * HPT);
         for (int r = 0; r < rounds; ++r) {
             if (r > 0) load_round<DV1, HPT>(a, hb + lo, n, r, u, sp);
@@ -1151,21 +1206,7 @@ __device__ __forceinline__ bool stage_hits_w(const TrackArgs &a, int nsec, int h
                 }
             }
         }
-        // exclusive prefix over the layer's buckets, offset by the layer's start:
-        // 512 buckets at a time, eight independent wavefront scans, then the carries
-        int carry = lo;
-        for (int b0 = 0; b0 < nb; b0 += 512) {
-            int v[8], incl[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = b0 + 64 * j + lane < nb ? (int)EL[b0 + 64 * j + lane] : 0;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) incl[j] = wave_inclusive_sum(v[j]);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                if (b0 + 64 * j + lane < nb) EL[b0 + 64 * j + lane] = (uint16_t)(carry + incl[j] - v[j]);
-                carry += __builtin_amdgcn_readlane(incl[j], 63);
-            }
-        }
+        scan_bounds(EL, nb, lo);
         // placing pass: EL[b] advances to the end of bucket b
         for (int r = 0; r < rounds; ++r) {
             if (rounds > 1) load_round<DV1, HPT>(a, hb + lo, n, r, u, sp);
