@@ -38,9 +38,12 @@ def signature(batch) -> str:
 
 
 def device_name() -> str:
+    """The device as the cache knows it: ISA name and compute-unit count (the
+    marketing name is not stable across drivers and tools)."""
     import torch
     p = torch.cuda.get_device_properties(0)
-    return f"{p.name}-{getattr(p, 'gcnArchName', 'gfx')}"
+    arch = str(getattr(p, "gcnArchName", "gfx")).split(":")[0]
+    return f"{arch}-{p.multi_processor_count}cu"
 
 
 def cache_key(batch, algorithm: int) -> str:

@@ -32,8 +32,9 @@ SQ_SETS = (
 SQ_BENCH = "python $REPO/bench.py --steps 3 --warmup 1 --no-plain --no-cpu-baseline --no-serve --no-copy-ceiling"
 
 
-def sq_commands():
-    return [f"rocprofv3 --pmc {c} --output-format csv -d $OUT/pmc_sq{k} -o sq -- {SQ_BENCH}"
+def sq_commands(config: int = 1):
+    bench = SQ_BENCH + ("" if config == 1 else f" --config {config} --no-dv1")
+    return [f"rocprofv3 --pmc {c} --output-format csv -d $OUT/pmc_sq{k} -o sq -- {bench}"
             for k, c in enumerate(SQ_SETS)]
 
 
@@ -41,7 +42,7 @@ def commands(steps: int = 10, config: int = 1):
     """The three profiler runs, each started in /tmp with TMPDIR=/tmp, $REPO
     set to the repository root and $OUT to the output directory; the trace
     run's stdout (the benchmark's JSON line) goes to $OUT/prof_bench.json."""
-    bench = BENCH.format(steps=steps) + ("" if config == 1 else f" --config {config}")
+    bench = BENCH.format(steps=steps) + ("" if config == 1 else f" --config {config} --no-dv1")
     d = "$OUT"
     return {
         "trace": f"rocprofv3 --kernel-trace --stats --output-format csv -d {d}/prof_trace -o trace -- {bench}"
@@ -135,7 +136,7 @@ def summarize(trace_dir, fetch_dir, write_dir, kernel_key, name, workload, algor
         m = {k: statistics.mean(v) for k, v in sq.items()}
         g = lambda k: m.get(k, float("nan"))
         lines += ["## Issue and stall counters of the dominant kernel (SQ, per dispatch)", "",
-                  "Commands:", ""] + [f"    {c}" for c in sq_commands()] + ["", "| counter | value |", "|---|---|"]
+                  "Commands:", ""] + [f"    {c}" for c in sq_commands(config)] + ["", "| counter | value |", "|---|---|"]
         lines += [f"| {k} | {v:.4g} |" for k, v in sorted(m.items())]
         lines += ["", "| derived | value |", "|---|---|",
                   f"| wave cycles waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES) | {g('SQ_WAIT_ANY') / g('SQ_WAVE_CYCLES'):.3f} |",
@@ -163,12 +164,15 @@ def summarize(trace_dir, fetch_dir, write_dir, kernel_key, name, workload, algor
 
 def kernel_key_id(key: str) -> str:
     return {"k_track<256, false, true, false, false>": "k_track_fused",
-            "k_track<256, false, true, true, false>": "k_track_fused_dv1"}.get(key, key)
+            "k_track<256, false, true, true, false>": "k_track_fused_dv1",
+            "k_track<256, false, false, false, false>": "k_track",
+            "k_vertex<256, false>": "k_vertex"}.get(key, key)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--print-commands", action="store_true")
+    ap.add_argument("--print-sq-commands", action="store_true")
     ap.add_argument("--dir", default="prof_out", help="output directory of the profiler runs ($OUT)")
     ap.add_argument("--kernel", default="k_track<256, false, true, false, false>")
     ap.add_argument("--name", default="k_track_fused_throughput_10k")
@@ -180,6 +184,10 @@ def main():
     if args.print_commands:
         for k, c in commands(args.steps, args.config).items():
             print(f"{k}\t{c}")
+        return
+    if args.print_sq_commands:
+        for c in sq_commands(args.config):
+            print(c)
         return
     ab = args.algorithmic_bytes
     workload = src = None
