@@ -307,7 +307,7 @@ ds_status ds_process_static(ds_ctx *ctx, const ds_events *ev, const ds_tracks *t
 
 /*
  * Launch tuning (used by the autotuner).  kernel: 0 = tracking, 1 = vertexing.
- * block: threads per workgroup (64, 128, 256, 512); wg_per_cu: persistent
+ * block: threads per workgroup (64, 128, 192 (tracking only), 256, 512); wg_per_cu: persistent
  * workgroups per compute unit (1..16); bins: hit bins per layer for the
  * window lookup (tracking only; 64..4096, power of two).  0 keeps a value.
  */

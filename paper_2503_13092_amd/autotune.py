@@ -25,8 +25,10 @@ from . import ds
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
-SPACE = dict(block=(128, 256, 512), wg_per_cu=(1, 2, 3, 4, 6), bins=(256, 512, 1024),
+SPACE = dict(block=(128, 192, 256, 512), wg_per_cu=(1, 2, 3, 4, 6), bins=(256, 512, 1024),
              order=(ds.DS_ORDER_INPUT, ds.DS_ORDER_LARGEST_FIRST))
+# the standalone vertexing launch (ds_vertex, and the step when it runs as two launches)
+VERTEX_SPACE = dict(block=(64, 128, 256, 512), wg_per_cu=(2, 4, 8, 16))
 
 
 def signature(batch) -> str:
@@ -71,6 +73,25 @@ def set_point(ctx, pt: Dict) -> None:
     ds.ds_set_launch(ctx, 0, pt["block"], pt["wg_per_cu"], pt["bins"])
     ds.ds_set_event_order(ctx, pt["order"])
     ds.ds_set_step_fusion(ctx, pt.get("fused", 1))
+    v = pt.get("vertex")
+    if v:
+        ds.ds_set_launch(ctx, 1, v["block"], v["wg_per_cu"], 0)
+
+
+def sweep_vertex(ctx, ev, tr, vt, score_max: float, reps: int = 5, stream=None, space=VERTEX_SPACE) -> List[Dict]:
+    """Times ds_vertex (graph mode) on the tracks in `tr` at every (block, wg_per_cu)."""
+    import torch
+    stream = stream or torch.cuda.current_stream()
+    out = []
+    for block, wpc in itertools.product(space["block"], space["wg_per_cu"]):
+        try:
+            ds.ds_set_launch(ctx, 1, block, wpc, 0)
+            ms = _time(lambda: ds.ds_vertex(ctx, ev, tr, score_max, vt, ds.DS_MODE_GRAPH, stream), stream, reps)
+        except ds.DsError as e:
+            out.append(dict(block=block, wg_per_cu=wpc, ms=None, error=str(e)))
+            continue
+        out.append(dict(block=block, wg_per_cu=wpc, ms=ms))
+    return out
 
 
 def sweep_process(ctx, ev, tr, vt, score_max: float, points: Iterable[Tuple[int, int, int, int]], reps: int = 5,
@@ -81,8 +102,6 @@ def sweep_process(ctx, ev, tr, vt, score_max: float, points: Iterable[Tuple[int,
     out = []
     for block, wpc, bins, order in points:
         pt = dict(block=block, wg_per_cu=wpc, bins=bins, order=order, fused=fused)
-        if (4 * bins) % block:
-            continue
         try:
             set_point(ctx, pt)
             ms = _time(lambda: ds.ds_process(ctx, ev, tr, vt, ds.DS_MODE_GRAPH, score_max=score_max,
@@ -121,6 +140,12 @@ def autotune(ctx, batch, ev, tr, vt, score_max: float, algorithm: int = 0, reps:
              path: Optional[str] = CACHE, space=SPACE, log=print) -> Dict:
     import torch
     stream = torch.cuda.current_stream()
+    # the vertexing launch first, on the tracks of one step
+    ds.ds_process(ctx, ev, tr, vt, ds.DS_MODE_GRAPH, score_max=score_max, stream=stream)
+    vres = sweep_vertex(ctx, ev, tr, vt, score_max, reps=reps, stream=stream)
+    vbest = min((r for r in vres if r["ms"] is not None), key=lambda r: r["ms"])
+    vpick = dict(block=vbest["block"], wg_per_cu=vbest["wg_per_cu"])
+    ds.ds_set_launch(ctx, 1, vpick["block"], vpick["wg_per_cu"], 0)
     pts = list(itertools.product(space["block"], space["wg_per_cu"], space["bins"], space["order"]))
     res = sweep_process(ctx, ev, tr, vt, score_max, pts, reps=reps, stream=stream)
     ok = [r for r in res if r["ms"] is not None]
@@ -138,9 +163,10 @@ def autotune(ctx, batch, ev, tr, vt, score_max: float, algorithm: int = 0, reps:
                                                     stream=stream), stream, 3 * reps)
     cands = [(confirm["best"], best), (confirm["unfused"], dict(best, fused=0)), (confirm["default"], default)]
     ms, pick = min(cands, key=lambda c: c[0])
+    pick = dict(pick, vertex=vpick)
     set_point(ctx, pick)
     entry = dict(best=pick, ms=round(ms, 4), default_ms=round(confirm["default"], 4), n_events=batch.n_events,
-                 when=round(time.time()))
+                 vertex_ms=round(vbest["ms"], 4), when=round(time.time()))
     if log:
         log(f"autotune alg{algorithm} {signature(batch)}: best {pick} {entry['ms']} ms "
             f"(default {entry['default_ms']} ms)")
@@ -151,7 +177,7 @@ def autotune(ctx, batch, ev, tr, vt, score_max: float, algorithm: int = 0, reps:
         with open(tmp, "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)
         os.replace(tmp, path)
-    return dict(entry, sweep=res)
+    return dict(entry, sweep=res, vertex_sweep=vres)
 
 
 def main(argv=None):

@@ -137,6 +137,7 @@ size_t track_lds(int hcap, int nb, int nb3, int block, int icap, int tcap)
 // k_vertex: the event's kept tracks, then the survivor ring of the pair loop
 size_t vertex_lds(int tcap, int block)
 {
+    // the ring is ds::vtx_ring<block>() ints: 8 * block for the power-of-two blocks the vertex kernel takes
     return round16((size_t)tcap * 24) + sizeof(int) * (size_t)(8 * block);
 }
 
@@ -253,6 +254,7 @@ hipError_t launch_track(int block, const ds::TrackArgs &a, const ds::DevGeom &G,
     switch (block) {
     case 64: return launch_track_b<64>(a, G, grid, lds, s);
     case 128: return launch_track_b<128>(a, G, grid, lds, s);
+    case 192: return launch_track_b<192>(a, G, grid, lds, s);
     case 256: return launch_track_b<256>(a, G, grid, lds, s);
     default: return launch_track_b<512>(a, G, grid, lds, s);
     }
@@ -291,7 +293,7 @@ hipError_t set_kernel_attributes()
         reinterpret_cast<const void *>(&ds::k_track<B, false, true, true>),                                 \
         reinterpret_cast<const void *>(&ds::k_track<B, false, true, false, true>),                          \
         reinterpret_cast<const void *>(&ds::k_track<B, false, true, true, true>)
-        DS_TRACK_FNS(64), DS_TRACK_FNS(128), DS_TRACK_FNS(256), DS_TRACK_FNS(512),
+        DS_TRACK_FNS(64), DS_TRACK_FNS(128), DS_TRACK_FNS(192), DS_TRACK_FNS(256), DS_TRACK_FNS(512),
 #undef DS_TRACK_FNS
         reinterpret_cast<const void *>(&ds::k_vertex<64, false>),
         reinterpret_cast<const void *>(&ds::k_vertex<128, false>),
@@ -337,12 +339,12 @@ ds_status plan_track(ds_ctx *c, const ds_events *ev, const ds_tracks *out, int f
     const int nbu = dv1 ? std::max(4, (4 * c->trk.bins - nsec - 4) / (3 * nsec)) : c->trk.bins;
     const int nb = dv1 ? nsec * nbu + 1 : nbu;
     const int nbu3 = dv1 ? 1 : nbu, nb3 = dv1 ? nsec + 1 : nb;
-    int hcap = round_up(std::max(ev->max_hits_per_event, 1), 64);
+    int hcap = round_up(std::max(ev->max_hits_per_event, 1), 16);
     if (hcap > 65535) return DS_E_CAPACITY;   // 16-bit LDS positions and bucket bounds
     const int block = c->trk.block;
     // items per chunk: room for ITEMS_PER_SEED per seed; a chunk shrinks when its seeds need more
     const int icap = std::max(block * ITEMS_PER_SEED, ds::MAX_L3);
-    const int tcap = vertex_fused ? round_up(std::max(ev->max_seeds_per_event, 1), 64) : 0;
+    const int tcap = vertex_fused ? round_up(std::max(ev->max_seeds_per_event, 1), 16) : 0;
     if (tcap > 65535) return DS_E_CAPACITY;
     size_t lds = track_lds(hcap, nb, nb3, block, icap, tcap);
     if (lds > LDS_LIMIT) return DS_E_CAPACITY;
@@ -1079,7 +1081,8 @@ ds_status ds_load_lines(ds_ctx *c, const float *w, size_t nw)
 ds_status ds_set_launch(ds_ctx *c, int kernel, int block, int wg_per_cu, int bins)
 {
     if (!c || (kernel != 0 && kernel != 1)) return DS_E_ARG;
-    if (block != 0 && block != 64 && block != 128 && block != 256 && block != 512) return DS_E_ARG;
+    if (block != 0 && block != 64 && block != 128 && block != 192 && block != 256 && block != 512) return DS_E_ARG;
+    if (kernel == 1 && block == 192) return DS_E_ARG;   // tracking only
     if (wg_per_cu < 0 || wg_per_cu > 16) return DS_E_ARG;
     if (bins != 0 && (kernel != 0 || bins < 64 || bins > 4096 || (bins & (bins - 1)))) return DS_E_ARG;
     std::lock_guard<std::mutex> lock(c->mu);
@@ -1088,7 +1091,6 @@ ds_status ds_set_launch(ds_ctx *c, int kernel, int block, int wg_per_cu, int bin
     if (block) n.block = block;
     if (wg_per_cu) n.wg_per_cu = wg_per_cu;
     if (bins) n.bins = bins;
-    if (kernel == 0 && (4 * n.bins) % n.block != 0) return DS_E_ARG;
     L = n;
     return DS_OK;
 }

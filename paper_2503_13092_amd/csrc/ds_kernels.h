@@ -1242,13 +1242,18 @@ __device__ __forceinline__ void vertex_extras(const DevGeom &G, const float *WLg
 // workgroup scan per chunk).  Whenever a workgroup's worth of survivors is
 // queued (and at the end) they are fitted together, a lane per pair (float64
 // Newton PCA), and the passing ones written in queue order: vertices come out
-// (i, j)-ordered, and the first vcap of them are kept.  ring: VTX_RING(BLOCK)
+// (i, j)-ordered, and the first vcap of them are kept.  ring: vtx_ring<BLOCK>()
 // ints.  XTR: also the masses and trigger-line scores of each vertex
 // (compiled only where they are asked for: their registers would otherwise
 // count against every fused launch).
 constexpr int VTX_PPT = 4;
 template <int BLOCK>
-constexpr int vtx_ring() { return 8 * BLOCK; }   // > BLOCK - 1 + VTX_PPT * BLOCK live entries
+constexpr int vtx_ring()   // a power of two above the BLOCK - 1 + VTX_PPT * BLOCK live entries
+{
+    int r = 1;
+    while (r < (VTX_PPT + 1) * BLOCK) r *= 2;
+    return r;
+}
 
 __device__ __forceinline__ bool pair_prescreen(const DevGeom &G, float4 A, float4 B)
 {
