@@ -131,14 +131,13 @@ size_t track_lds(int hcap, int nb, int nb3, int block, int icap, int tcap)
     off += (size_t)block * 8;
     off = round16(off + (size_t)block * 4);
     off = round16(off + (size_t)icap * 4);
-    return off + (size_t)icap * 8 + (size_t)tcap * 24;
+    return round16(off + (size_t)icap * 8) + ds::kept_lds_bytes(tcap);
 }
 
 // k_vertex: the event's kept tracks, then the survivor ring of the pair loop
 size_t vertex_lds(int tcap, int block)
 {
-    // the ring is ds::vtx_ring<block>() ints: 8 * block for the power-of-two blocks the vertex kernel takes
-    return round16((size_t)tcap * 24) + sizeof(int) * (size_t)(8 * block);
+    return ds::kept_lds_bytes(tcap) + sizeof(int) * (size_t)ds::vtx_ring_ints(block);
 }
 
 int round_up(int v, int m) { return ((v + m - 1) / m) * m; }
@@ -345,11 +344,14 @@ ds_status plan_track(ds_ctx *c, const ds_events *ev, const ds_tracks *out, int f
     // items per chunk: room for ITEMS_PER_SEED per seed; a chunk shrinks when its seeds need more
     const int icap = std::max(block * ITEMS_PER_SEED, ds::MAX_L3);
     const int tcap = vertex_fused ? round_up(std::max(ev->max_seeds_per_event, 1), 16) : 0;
-    if (tcap > 65535) return DS_E_CAPACITY;
+    if (tcap > 32767) return DS_E_CAPACITY;   // 15-bit kept-track indices
     size_t lds = track_lds(hcap, nb, nb3, block, icap, tcap);
     if (lds > LDS_LIMIT) return DS_E_CAPACITY;
     // the network's feature tiles reuse the seed-constant ... item region
     if (track_lds(0, 0, 0, block, icap, 0) - 16 < (size_t)(block / 64) * ds::MLP_TILE * 4) return DS_E_CAPACITY;
+    // ... and so does the fused pair loop's survivor ring
+    if (vertex_fused && track_lds(0, 0, 0, block, icap, 0) - 16 < sizeof(int) * (size_t)ds::vtx_ring_ints(block))
+        return DS_E_CAPACITY;
     ds::TrackArgs &a = p->a;
     std::memset(&a, 0, sizeof(a));
     a.n_events = ev->n_events;
@@ -423,7 +425,7 @@ ds_status plan_vertex(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, floa
                       int *counters, VertexPlan *p)
 {
     int tcap = round_up(std::max(ev->max_seeds_per_event, 1), 64);
-    if (tcap > 65535) return DS_E_CAPACITY;
+    if (tcap > 32767) return DS_E_CAPACITY;   // 15-bit kept-track indices
     size_t lds = vertex_lds(tcap, c->vtx.block);
     if (lds > LDS_LIMIT) return DS_E_CAPACITY;
     ds::VertexArgs &a = p->a;

@@ -1161,8 +1161,8 @@ __device__ __forceinline__ void scan_bounds(uint16_t *EL, int n, int carry)
 }
 
 // Stage one event's hits a wavefront per layer: each wavefront counts its
-// layer's hits into the layer's buckets, scans them (64 buckets per step, DPP
-// sums) and places the hits, with no workgroup barrier until the end: a
+// layer's hits into the layer's buckets, scans them (two buckets per lane per
+// step, DPP sums) and places the hits, with no workgroup barrier until the end: a
 // wavefront's LDS operations complete in order.  Same result as a workgroup
 // counting sort: E[b] = start of bucket b, E[3*nb + nb3] = count.  *s_bad must be 0
 // on entry.
@@ -1234,25 +1234,85 @@ __device__ __forceinline__ bool pca64(const DevGeom &G, double x1, double y1, do
 __device__ __forceinline__ void vertex_extras(const DevGeom &G, const float *WLg, float4 A, float4 B, double g1, double g2,
                                      float q1, float q2, double s, double t, float4 V, float out[6]);
 
-// Vertexing of one event by the whole workgroup, from the kept tracks in LDS
-// (slot order), pairs (a < b) in row-major order.  Each lane takes VTX_PPT
-// consecutive pairs of a chunk (one unranking, then steps along the row):
-// opposite charge and the float32 straight-line prescreen; the chunk's
-// survivors are appended, in pair order, to a ring of pair codes in LDS (one
-// workgroup scan per chunk).  Whenever a workgroup's worth of survivors is
-// queued (and at the end) they are fitted together, a lane per pair (float64
-// Newton PCA), and the passing ones written in queue order: vertices come out
-// (i, j)-ordered, and the first vcap of them are kept.  ring: vtx_ring<BLOCK>()
-// ints.  XTR: also the masses and trigger-line scores of each vertex
-// (compiled only where they are asked for: their registers would otherwise
-// count against every fused launch).
-constexpr int VTX_PPT = 4;
-template <int BLOCK>
-constexpr int vtx_ring()   // a power of two above the BLOCK - 1 + VTX_PPT * BLOCK live entries
+// Vertexing of one event by the whole workgroup.  Only opposite-charge pairs
+// are visited: the kept tracks sit in LDS split by seed charge (Kept below),
+// and row r of the pair triangle (the r-th kept track in slot order) holds its
+// opposite-charge partners of higher slot, which are a run of the other charge
+// list; rows are concatenated in slot order, so pair ranks follow (i, j)
+// order.  Each lane takes VTX_PPT consecutive pairs of a chunk (a binary
+// search of the row starts, then steps along the row) and applies the float32
+// straight-line prescreen; the chunk's survivors are appended, in pair order,
+// to a ring of pair codes in LDS (one workgroup scan per chunk).  Whenever a
+// workgroup's worth of survivors is queued (and at the end) they are fitted
+// together, a lane per pair (float64 Newton PCA), and the passing ones
+// written in queue order: vertices come out (i, j)-ordered, and the first vcap
+// of them are kept.  ring: vtx_ring<BLOCK>() ints.  XTR: also the masses and
+// trigger-line scores of each vertex (compiled only where they are asked for:
+// their registers would otherwise count against every fused launch).
+// VTX_PPT = 5: neighbouring lanes read partners 5 entries (80 bytes) apart,
+// which spreads a wavefront's 16-byte LDS reads over distinct banks.
+constexpr int VTX_PPT = 5;
+__host__ __device__ constexpr int vtx_ring_ints(int block)   // a power of two above the block - 1 + VTX_PPT * block live entries
 {
     int r = 1;
-    while (r < (VTX_PPT + 1) * BLOCK) r *= 2;
+    while (r < (VTX_PPT + 1) * block) r *= 2;
     return r;
+}
+template <int BLOCK>
+constexpr int vtx_ring() { return vtx_ring_ints(BLOCK); }
+
+// Kept tracks of one event in LDS, the vertexing input.  Positive-charge
+// tracks fill st/q/slot from the front and negative ones from the back, each
+// list in slot order (the o-th negative at tcap - 1 - o).  row[r] describes
+// the r-th kept track in slot order: its index o in its charge list, | 0x8000
+// when positive; the tracks of the other charge before it number r - o, so
+// its partners of higher slot are that list's entries from r - o on.  R[r] is
+// the rank of row r's first pair (R[n] = all pairs), filled by the vertexing.
+struct Kept {
+    float4 *st;      // x, y, tx, ty at the UT midpoint
+    float *q;        // fitted q/p
+    int *slot;       // slot << 1 | positive seed charge
+    int *R;          // tcap + 1 row starts
+    uint16_t *row;   // tcap row descriptors
+};
+
+__host__ __device__ constexpr size_t kept_lds_bytes(int tcap)
+{
+    return tcap > 0 ? ((size_t)tcap * 30 + 4 + 15) & ~(size_t)15 : 0;
+}
+
+__device__ __forceinline__ Kept kept_carve(unsigned char *base, int tcap)
+{
+    Kept k;
+    k.st = reinterpret_cast<float4 *>(base);
+    k.q = reinterpret_cast<float *>(base + (size_t)tcap * 16);
+    k.slot = reinterpret_cast<int *>(base + (size_t)tcap * 20);
+    k.R = reinterpret_cast<int *>(base + (size_t)tcap * 24);
+    k.row = reinterpret_cast<uint16_t *>(base + (size_t)tcap * 28 + 4);
+    return k;
+}
+
+// Appends this chunk's kept tracks (at most one per lane, lanes in slot
+// order).  n and np (kept so far, positive so far) are workgroup-uniform and
+// advanced; tcap < 32768 (LDS holds far fewer).
+template <int BLOCK>
+__device__ __forceinline__ void kept_append(const Kept &K, int tcap, bool kept, bool positive, float4 st, float q,
+                                            int slot, int &n, int &np, int *s_wsum)
+{
+    int tot;
+    const int ex = block_exclusive_scan<BLOCK>(kept ? (positive ? 0x10001 : 1) : 0, s_wsum, &tot);
+    if (kept) {
+        const int r = n + (ex & 0xffff);
+        const int pb = np + (ex >> 16);   // positive tracks before this one
+        const int o = positive ? pb : r - pb;
+        const int pos = positive ? o : tcap - 1 - o;
+        K.st[pos] = st;
+        K.q[pos] = q;
+        K.slot[pos] = (slot << 1) | (positive ? 1 : 0);
+        K.row[r] = (uint16_t)(o | (positive ? 0x8000 : 0));
+    }
+    n += tot & 0xffff;
+    np += tot >> 16;
 }
 
 __device__ __forceinline__ bool pair_prescreen(const DevGeom &G, float4 A, float4 B)
@@ -1267,17 +1327,36 @@ __device__ __forceinline__ bool pair_prescreen(const DevGeom &G, float4 A, float
 
 // Args: TrackArgs (fused step) or VertexArgs (standalone): the vertex outputs
 // vcap, vcount, vi, vj, vx, vy, vz, vdoca, voverflow, the extras' outputs, WL
-// and the seeds' sqop under the same names.
+// and the seeds' sqop under the same names.  n kept tracks, np of them
+// positive, in K (kept_append); the row list is visible to every lane.
 template <int BLOCK, bool XTR, typename Args>
-__device__ __forceinline__ void vertex_event_block(const Args &a, const DevGeom &G, int e, int s0, int n,
-                                          const float4 *kst, const float *kq, const int *kslot, int *ring,
-                                          int *s_wsum)
+__device__ __forceinline__ void vertex_event_block(const Args &a, const DevGeom &G, int e, int s0, int n, int np,
+                                          const Kept &K, int tcap, int *ring, int *s_wsum)
 {
     constexpr int CH = VTX_PPT * BLOCK, RING = vtx_ring<BLOCK>();
     static_assert((RING & (RING - 1)) == 0, "ring size a power of two");
     const int tid = threadIdx.x;
     const bool curved = (G.fp != 0.0);
-    const int npairs = n * (n - 1) / 2;
+    const int nn = n - np;   // negative tracks
+    // row starts: row r pairs with the other charge list's entries from r - o on
+    int npairs = 0;
+    if (np > 0 && nn > 0) {
+        for (int r0 = 0; r0 < n; r0 += BLOCK) {
+            const int r = r0 + tid;
+            int len = 0;
+            if (r < n) {
+                const int d = K.row[r];
+                len = ((d & 0x8000) ? nn : np) - (r - (d & 0x7fff));
+            }
+            int tot;
+            const int ex = block_exclusive_scan<BLOCK>(len, s_wsum, &tot);
+            if (r < n) K.R[r] = npairs + ex;
+            npairs += tot;
+        }
+        if (tid == 0) K.R[n] = npairs;
+        lds_barrier();
+    }
+    const int top = n > 1 ? 1 << (31 - __builtin_clz(n - 1)) : 0;   // highest power of two below n
     int out_n = 0, head = 0, qn = 0;   // workgroup-uniform
     for (int chunk = 0;;) {
         const bool more = chunk < npairs;
@@ -1286,25 +1365,38 @@ __device__ __forceinline__ void vertex_event_block(const Args &a, const DevGeom 
             int code[VTX_PPT];
             unsigned m = 0;
             if (k0 < npairs) {
-                int pa, pb;
-                unrank_pair(k0, n, pa, pb);
-                float4 A = kst[pa];
-                int sa = kslot[pa];
+                // row of k0: the last r with R[r] <= k0 (a row without pairs starts where the next one does)
+                int r = 0;
+                for (int step = top; step > 0; step >>= 1)
+                    if (r + step < n && K.R[r + step] <= k0) r += step;
+                int rend = K.R[r + 1], c = k0 - K.R[r];
+                int d = K.row[r];
+                int pa = (d & 0x8000) ? (d & 0x7fff) : tcap - 1 - (d & 0x7fff);
+                float4 A = K.st[pa];
+                int k = k0;
 #pragma unroll
                 for (int j = 0; j < VTX_PPT; ++j) {
-                    if (j > 0 && ++pb >= n) {   // next row
-                        ++pa;
-                        pb = pa + 1;
-                        A = kst[pa < n ? pa : 0];
-                        sa = kslot[pa < n ? pa : 0];
+                    if (j > 0) {
+                        ++k;
+                        ++c;
+                        if (k >= rend && k < npairs) {   // on to the next row that has pairs
+                            do {
+                                ++r;
+                            } while (K.R[r + 1] <= k);
+                            rend = K.R[r + 1];
+                            c = k - K.R[r];
+                            d = K.row[r];
+                            pa = (d & 0x8000) ? (d & 0x7fff) : tcap - 1 - (d & 0x7fff);
+                            A = K.st[pa];
+                        }
                     }
+                    // past the last pair nothing is read out of range; the prescreen runs on every lane
+                    const bool valid = k < npairs;
+                    const int q = r - (d & 0x7fff) + c;   // partner index in the other list
+                    const int pb = valid ? ((d & 0x8000) ? tcap - 1 - q : q) : pa;
                     code[j] = (pa << 16) | pb;
-                    // past the last pair (pb may reach n) nothing is read out of range
-                    const bool valid = k0 + j < npairs;
-                    const int pbs = valid ? pb : 0;
-                    const bool surv = valid && ((sa ^ kslot[pbs]) & 1) != 0 &&
-                                      (curved || pair_prescreen(G, A, kst[pbs]));
-                    m |= surv ? 1u << j : 0u;
+                    const bool near = curved | pair_prescreen(G, A, K.st[pb]);
+                    m |= (valid & near) ? 1u << j : 0u;
                 }
             }
             int tot;
@@ -1326,9 +1418,9 @@ __device__ __forceinline__ void vertex_event_block(const Args &a, const DevGeom 
                 const int c = ring[(head + tid) & (RING - 1)];
                 ia = c >> 16;
                 ib = c & 0xffff;
-                const float4 A = kst[ia], B = kst[ib];
-                const double g1 = -G.fp * (G.gc0 + G.gc1 * ((double)kq[ia] * 1e-3));
-                const double g2 = -G.fp * (G.gc0 + G.gc1 * ((double)kq[ib] * 1e-3));
+                const float4 A = K.st[ia], B = K.st[ib];
+                const double g1 = -G.fp * (G.gc0 + G.gc1 * ((double)K.q[ia] * 1e-3));
+                const double g2 = -G.fp * (G.gc0 + G.gc1 * ((double)K.q[ib] * 1e-3));
                 double vx, vy, vz, dd, ps, pt;
                 const bool good = pca64(G, A.x, A.y, A.z, A.w, g1, B.x, B.y, B.z, B.w, g2, vx, vy, vz, dd, ps, pt);
                 pass = (good && (dd < G.doca_max)) ? 1 : 0;
@@ -1341,19 +1433,19 @@ __device__ __forceinline__ void vertex_event_block(const Args &a, const DevGeom 
                 const int m2 = out_n + opos;
                 if (m2 < a.vcap) {
                     const size_t o = (size_t)e * (size_t)a.vcap + (size_t)m2;
-                    a.vi[o] = kslot[ia] >> 1;
-                    a.vj[o] = kslot[ib] >> 1;
+                    a.vi[o] = K.slot[ia] >> 1;
+                    a.vj[o] = K.slot[ib] >> 1;
                     a.vx[o] = R.x;
                     a.vy[o] = R.y;
                     a.vz[o] = R.z;
                     a.vdoca[o] = R.w;
                     if constexpr (XTR) {
-                        const float4 TA = kst[ia], TB = kst[ib];
-                        const double g1 = -G.fp * (G.gc0 + G.gc1 * ((double)kq[ia] * 1e-3));
-                        const double g2 = -G.fp * (G.gc0 + G.gc1 * ((double)kq[ib] * 1e-3));
+                        const float4 TA = K.st[ia], TB = K.st[ib];
+                        const double g1 = -G.fp * (G.gc0 + G.gc1 * ((double)K.q[ia] * 1e-3));
+                        const double g2 = -G.fp * (G.gc0 + G.gc1 * ((double)K.q[ib] * 1e-3));
                         float ex[6];
-                        vertex_extras(G, a.WL, TA, TB, g1, g2, a.sqop[s0 + (kslot[ia] >> 1)],
-                                      a.sqop[s0 + (kslot[ib] >> 1)], ST.x, ST.y, R, ex);
+                        vertex_extras(G, a.WL, TA, TB, g1, g2, a.sqop[s0 + (K.slot[ia] >> 1)],
+                                      a.sqop[s0 + (K.slot[ib] >> 1)], ST.x, ST.y, R, ex);
                         a.m_pipi[o] = ex[0];
                         a.m_ppi[o] = ex[1];
                         a.line0[o] = ex[2];
@@ -1419,13 +1511,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2
     uint32_t *it_desc = reinterpret_cast<uint32_t *>(smem + off);
     off = (off + (size_t)a0.icap * 4 + 15) & ~(size_t)15;
     unsigned long long *it_hits = reinterpret_cast<unsigned long long *>(smem + off);
-    off += (size_t)a0.icap * 8;
-    // fused vertexing: kept tracks of the event (its survivor ring aliases the seed constants)
-    float4 *kst = reinterpret_cast<float4 *>(smem + off);
-    float *kq = reinterpret_cast<float *>(smem + off + (size_t)a0.tcap * 16);
-    int *kslot = reinterpret_cast<int *>(smem + off + (size_t)a0.tcap * 20);
+    off = (off + (size_t)a0.icap * 8 + 15) & ~(size_t)15;
+    // fused vertexing: kept tracks of the event (its survivor ring aliases the seed constants);
+    // the list's pointers are derived where they are used
+    const uint32_t kept_off = (uint32_t)off;
     __shared__ int s_nx[8];   // next event and its offsets (fetch_event)
-    __shared__ int s_bad, s_nacc, s_nitems, s_nkept;
+    __shared__ int s_bad, s_nacc, s_nitems, s_nkept, s_nkpos;
     __shared__ int s_long;   // Dv1: a seed of the chunk has more than 128 UTbX hits
     __shared__ int s_wsum[BLOCK / 64];
     const int tid = threadIdx.x;
@@ -1470,7 +1561,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2
             lds_barrier();
             continue;
         }
-        if (VTX && tid == 0) s_nkept = 0;
+        if (VTX && tid == 0) s_nkept = s_nkpos = 0;
         int hl[4];
 #pragma unroll
         for (int L = 0; L < 4; ++L) hl[L] = ho[L] - ho[0];
@@ -1821,25 +1912,24 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2
             }
             const bool kept = VTX && won && t.score < a.score_max;
             if (VTX) {
-                // kept tracks appended in slot order
-                int ktot;
-                const int kpos = block_exclusive_scan<BLOCK>(kept ? 1 : 0, s_wsum, &ktot);
-                if (kept) {
-                    const int k = s_nkept + kpos;
-                    kst[k] = make_float4(t.x, t.y, t.tx, t.ty);
-                    kq[k] = t.qop;
-                    kslot[k] = ((i - s0) << 1) | (sd.qop > 0.0f ? 1 : 0);
-                }
+                // kept tracks appended in slot order, split by seed charge
+                int nk = s_nkept, nkp = s_nkpos;
+                const int tcap = kernel_args<TrackKernArgs>().a.tcap;
+                kept_append<BLOCK>(kept_carve(smem + kept_off, tcap), tcap, kept, sd.qop > 0.0f, make_float4(t.x, t.y, t.tx, t.ty), t.qop, i - s0,
+                                   nk, nkp, s_wsum);
                 lds_barrier();
-                if (tid == 0) s_nkept += ktot;
+                if (tid == 0) {
+                    s_nkept = nk;
+                    s_nkpos = nkp;
+                }
             }
             lds_barrier();
             sc0 += nacc;
         }
         if (VTX) {
             const TrackKernArgs &Kv = kernel_args<TrackKernArgs>();
-            vertex_event_block<BLOCK, XTR>(Kv.a, Kv.G, e, s0, s_nkept, kst, kq, kslot, reinterpret_cast<int *>(s_c),
-                                           s_wsum);
+            vertex_event_block<BLOCK, XTR>(Kv.a, Kv.G, e, s0, s_nkept, s_nkpos, kept_carve(smem + kept_off, Kv.a.tcap),
+                                           Kv.a.tcap, reinterpret_cast<int *>(s_c), s_wsum);
         }
     }
     const TrackArgs &a = kernel_args<TrackKernArgs>().a;
@@ -2094,15 +2184,24 @@ __device__ __forceinline__ bool pca64(const DevGeom &G, double x1, double y1, do
     return true;
 }
 
-// Row-major rank k of the pair (a, b), a < b < n, back to (a, b).
+// Row-major rank k of the pair (a, b), a < b < n, back to (a, b).  Row r
+// starts at rank start(r) = r (2n - r - 1) / 2, and the row of k is the floor
+// of the smaller root of start(r) = k.  That root is taken in float32: for
+// fewer than 2^25 pairs the rounded discriminant is off by at most 8 plus a
+// relative 2^-24, so the root is off by less than 1.5 rows, and two exact
+// integer steps each way land on the row.  The kept tracks of one event fit
+// in LDS (24 bytes each), so n stays far below the 8192 this needs.
 __device__ __forceinline__ void unrank_pair(int k, int n, int &pa, int &pb)
 {
-    const double tn = 2.0 * n - 1.0;
-    int r = (int)floor((tn - sqrt(fmax(tn * tn - 8.0 * (double)k, 0.0))) * 0.5);
+    const float tn = 2.0f * (float)n - 1.0f;
+    const float d = fmaxf(fmaf(tn, tn, -8.0f * (float)k), 0.0f);
+    int r = (int)((tn - __builtin_amdgcn_sqrtf(d)) * 0.5f);
     r = max(0, min(r, n - 2));
-    auto start = [n](int q) { return q * (2 * n - q - 1) / 2; };
-    while (r + 1 <= n - 2 && start(r + 1) <= k) ++r;
-    while (r > 0 && start(r) > k) --r;
+    auto start = [n](int q) { return (int)((unsigned)(q * (2 * n - q - 1)) >> 1); };
+    r += (r < n - 2 && start(r + 1) <= k) ? 1 : 0;
+    r += (r < n - 2 && start(r + 1) <= k) ? 1 : 0;
+    r -= (r > 0 && start(r) > k) ? 1 : 0;
+    r -= (r > 0 && start(r) > k) ? 1 : 0;
     pa = r;
     pb = k - start(r) + r + 1;
 }
@@ -2167,31 +2266,16 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ int wave_exclusive_scan(int v, int *total)
-{
-    const int x = wave_inclusive_sum(v);
-    *total = __builtin_amdgcn_readlane(x, 63);
-    return x - v;
-}
-
-// Vertexing: every wavefront works on its own events (work-stealing), so a
-// small event costs no workgroup barrier.  Per event: kept tracks compacted in
-// slot order into the wave's LDS tile, pairs (a < b) visited in row-major
-// chunks of 64*PPT, a float32 straight-line prescreen, float64 Newton PCA of
-// the survivors, and an order-preserving compaction, so vertices come out in
-// (i, j) order.
 // Standalone vertexing (ds_vertex): a workgroup per event (work-stolen); the
 // event's kept tracks (nhits > 0, score < score_max) are compacted into LDS in
 // slot order, then the pairs go through vertex_event_block, the routine of the
-// fused step.  LDS: kept tracks (24 B each, tcap of them) and the survivor ring.
+// fused step.  LDS: kept tracks (kept_lds_bytes(tcap)) and the survivor ring.
 template <int BLOCK, bool XTR>
 __global__ __launch_bounds__(BLOCK) void k_vertex(VertexArgs a, DevGeom G)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    float4 *kst = reinterpret_cast<float4 *>(smem);
-    float *kq = reinterpret_cast<float *>(smem + (size_t)a.tcap * 16);
-    int *kslot = reinterpret_cast<int *>(smem + (size_t)a.tcap * 20);
-    int *ring = reinterpret_cast<int *>(smem + (((size_t)a.tcap * 24 + 15) & ~(size_t)15));
+    const Kept K = kept_carve(smem, a.tcap);
+    int *ring = reinterpret_cast<int *>(smem + kept_lds_bytes(a.tcap));
     __shared__ int s_e;
     __shared__ int s_wsum[BLOCK / 64];
     const int tid = threadIdx.x;
@@ -2215,30 +2299,23 @@ __global__ __launch_bounds__(BLOCK) void k_vertex(VertexArgs a, DevGeom G)
             }
             continue;
         }
-        // kept tracks, compacted in slot order (slot << 1 | positive seed charge)
-        int n = 0;
+        // kept tracks, in slot order per seed charge
+        int n = 0, np = 0;
         for (int base = s0; base < s1; base += BLOCK) {
             const int i = base + tid;
             const bool kept = (i < s1) && (a.nhits[i] > 0) && (a.score[i] < a.score_max);
             float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             float qv = 0.0f;
-            int pos_q = 0;
+            bool positive = false;
             if (kept) {
                 v = make_float4(a.x[i], a.y[i], a.tx[i], a.ty[i]);
                 qv = a.qop[i];
-                pos_q = a.sqop[i] > 0.0f ? 1 : 0;
+                positive = a.sqop[i] > 0.0f;
             }
-            int tot;
-            const int pos = block_exclusive_scan<BLOCK>(kept ? 1 : 0, s_wsum, &tot);
-            if (kept) {
-                kst[n + pos] = v;
-                kq[n + pos] = qv;
-                kslot[n + pos] = ((i - s0) << 1) | pos_q;
-            }
-            n += tot;
+            kept_append<BLOCK>(K, a.tcap, kept, positive, v, qv, i - s0, n, np, s_wsum);
         }
         lds_barrier();   // the kept tracks are visible
-        vertex_event_block<BLOCK, XTR>(a, G, e, s0, n, kst, kq, kslot, ring, s_wsum);
+        vertex_event_block<BLOCK, XTR>(a, G, e, s0, n, np, K, a.tcap, ring, s_wsum);
         lds_barrier();   // the event's LDS is free again
     }
     if (a.ev_single < 0 && tid == 0) {
