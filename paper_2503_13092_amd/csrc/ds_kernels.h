@@ -1227,7 +1227,6 @@ __device__ __forceinline__ bool stage_hits_w(const TrackArgs &a, int nsec, int h
     return *s_bad == 0;
 }
 
-__device__ __forceinline__ void unrank_pair(int k, int n, int &pa, int &pb);
 __device__ __forceinline__ bool pca64(const DevGeom &G, double x1, double y1, double tx1, double ty1, double g1, double x2,
                              double y2, double tx2, double ty2, double g2, double &vx, double &vy, double &vz,
                              double &doca, double &s_out, double &t_out);
@@ -2182,28 +2181,6 @@ __device__ __forceinline__ bool pca64(const DevGeom &G, double x1, double y1, do
     s_out = s;
     t_out = t;
     return true;
-}
-
-// Row-major rank k of the pair (a, b), a < b < n, back to (a, b).  Row r
-// starts at rank start(r) = r (2n - r - 1) / 2, and the row of k is the floor
-// of the smaller root of start(r) = k.  That root is taken in float32: for
-// fewer than 2^25 pairs the rounded discriminant is off by at most 8 plus a
-// relative 2^-24, so the root is off by less than 1.5 rows, and two exact
-// integer steps each way land on the row.  The kept tracks of one event fit
-// in LDS (24 bytes each), so n stays far below the 8192 this needs.
-__device__ __forceinline__ void unrank_pair(int k, int n, int &pa, int &pb)
-{
-    const float tn = 2.0f * (float)n - 1.0f;
-    const float d = fmaxf(fmaf(tn, tn, -8.0f * (float)k), 0.0f);
-    int r = (int)((tn - __builtin_amdgcn_sqrtf(d)) * 0.5f);
-    r = max(0, min(r, n - 2));
-    auto start = [n](int q) { return (int)((unsigned)(q * (2 * n - q - 1)) >> 1); };
-    r += (r < n - 2 && start(r + 1) <= k) ? 1 : 0;
-    r += (r < n - 2 && start(r + 1) <= k) ? 1 : 0;
-    r -= (r > 0 && start(r) > k) ? 1 : 0;
-    r -= (r > 0 && start(r) > k) ? 1 : 0;
-    pa = r;
-    pb = k - start(r) + r + 1;
 }
 
 // Invariant masses of a vertex (pi+ pi-, and p pi with the faster track as the
