@@ -36,6 +36,10 @@ WORKLOADS = {
 }
 
 
+# the workload part of the names of the rocprofv3 summaries under profiles/
+PROFILE_TAG = {1: "throughput_10k", 2: "uneven_20k", 4: "stress_5k"}
+
+
 def kernel_source_hash() -> str:
     from paper_2503_13092_amd.build_lib import kernel_source_hash as h
     return h()
@@ -100,9 +104,10 @@ def prescreen_survivors(batch, trk, score_max, doca_max, curved, margin=0.1, chu
     return total
 
 
-def stored_traffic(kernel: str, src_hash: str):
-    """HBM traffic per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source."""
+def stored_traffic(summary: str, src_hash: str):
+    """HBM traffic per launch from the committed rocprofv3 counter summary of
+    that name (kernel and workload), if it was taken on the current kernel
+    source."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -110,7 +115,7 @@ def stored_traffic(kernel: str, src_hash: str):
         d = json.load(open(p))
     except Exception:
         return None
-    e = d.get(kernel)
+    e = d.get(summary)
     if not e or e.get("source_hash") != src_hash:
         return None
     return e.get("bytes_per_launch")
@@ -306,7 +311,7 @@ def main():
         step_bytes = bpe * E
         kms, kname, kkey = trk_ms, "k_track: hit staging, search, fit and ghost-killer MLP", "k_track"
     achieved = step_bytes / (kms * 1e-3) / 1e9
-    traffic = stored_traffic(kkey, src_hash) if args.config == 1 else None
+    traffic = stored_traffic(f"{kkey}_{PROFILE_TAG.get(args.config, f'config{args.config}')}", src_hash)
     roofline = dict(bound="hbm", achieved=round(achieved, 2), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 5), traffic=traffic, kernel=kname,
                     kernel_ms=round(kms, 4), algorithmic_bytes_per_launch=round(step_bytes))
@@ -385,7 +390,7 @@ def main():
         ab1 = bpe * E + 24.0 * nv1 + 4.0 * E + 1.0 * batch.n_hits   # + the Y sector byte of every hit
         out["dv1"] = dict(events_per_s=round(E * args.steps / d1, 1), kernel_ms=round(ms1, 4),
                           achieved_GBs=round(ab1 / (ms1 * 1e-3) / 1e9, 2), algorithmic_bytes_per_launch=round(ab1),
-                          traffic=stored_traffic("k_track_fused_dv1", src_hash),
+                          traffic=stored_traffic("k_track_fused_dv1_throughput_10k", src_hash),
                           tracks=int(np.sum(nh1 > 0)), vertices=nv1,
                           flags=int(tr.flags.item()) | int(vt.flags.item()),
                           launch="ds_process, algorithm 1: one fused persistent launch, hipGraph replay",

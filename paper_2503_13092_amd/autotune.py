@@ -28,7 +28,7 @@ CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache
 SPACE = dict(block=(128, 192, 256, 512), wg_per_cu=(1, 2, 3, 4, 6), bins=(256, 512, 1024),
              order=(ds.DS_ORDER_INPUT, ds.DS_ORDER_LARGEST_FIRST))
 # the standalone vertexing launch (ds_vertex, and the step when it runs as two launches)
-VERTEX_SPACE = dict(block=(64, 128, 256, 512), wg_per_cu=(2, 4, 8, 16))
+VERTEX_SPACE = dict(block=(64, 128, 256, 512), wg_per_cu=(2, 4, 5, 6, 8, 16))
 
 
 def signature(batch) -> str:

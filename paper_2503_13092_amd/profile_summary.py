@@ -153,20 +153,25 @@ def summarize(trace_dir, fetch_dir, write_dir, kernel_key, name, workload, algor
         f.write("\n".join(lines))
     tj = os.path.join(out_dir, "traffic.json")
     d = json.load(open(tj)) if os.path.exists(tj) else {}
-    d[kernel_key_id(kernel_key)] = dict(source_hash=src, bytes_per_launch=round(fetch_b + write_b),
-                                        read_bytes=round(fetch_b), write_bytes=round(write_b),
-                                        fetch_factor=round(ff, 4), write_factor=round(fw, 4),
-                                        avg_ns=round(avg_ns), workload=workload, summary=f"{name}.md")
+    d[name] = dict(kernel=kernel_key_id(kernel_key), config=config, source_hash=src,
+                   bytes_per_launch=round(fetch_b + write_b),
+                   read_bytes=round(fetch_b), write_bytes=round(write_b),
+                   fetch_factor=round(ff, 4), write_factor=round(fw, 4),
+                   avg_ns=round(avg_ns), workload=workload, summary=f"{name}.md")
     with open(tj, "w") as f:
         json.dump(d, f, indent=1, sort_keys=True)
     return d
 
 
 def kernel_key_id(key: str) -> str:
-    return {"k_track<256, false, true, false, false>": "k_track_fused",
-            "k_track<256, false, true, true, false>": "k_track_fused_dv1",
-            "k_track<256, false, false, false, false>": "k_track",
-            "k_vertex<256, false>": "k_vertex"}.get(key, key)
+    """Short name of a kernel instantiation: k_track<block, candidate rows,
+    fused vertexing, Dv1, vertex extras>, k_vertex<block, extras>."""
+    if key.startswith("k_track<"):
+        f = [x.strip() for x in key[len("k_track<"):-1].split(",")]
+        return "k_track" + ("_fused" if f[2] == "true" else "") + ("_dv1" if f[3] == "true" else "")
+    if key.startswith("k_vertex<"):
+        return "k_vertex"
+    return key
 
 
 def main():
