@@ -122,22 +122,36 @@ ds_status dev_err(hipError_t e) { return e == hipSuccess ? DS_OK : DS_E_DEVICE; 
 
 size_t round16(size_t v) { return (v + 15) & ~size_t(15); }
 
-size_t track_lds(int hcap, int nb, int nb3, int block, int icap, int tcap)
+// Dynamic LDS of the tracking kernel, mirroring its carve: hits, bucket
+// bounds, then the seed constants ... item buffers (one region: phase C's
+// feature tiles and the fused vertexing's survivor ring and row table reuse
+// it), then the fused vertexing's kept tracks.
+struct TrackLayout {
+    size_t sc;      // seed constants: start of the reusable region
+    size_t kept;    // its end: the kept tracks
+    size_t total;
+};
+
+TrackLayout track_layout(int hcap, int nb, int nb3, int block, int icap, int tcap)
 {
+    TrackLayout L;
     size_t off = (size_t)hcap * 4;
     off = round16(off + (size_t)hcap * 2);
     off = round16(off + (size_t)(3 * nb + nb3 + 1) * 2);
+    L.sc = off;
     off += (size_t)block * sizeof(ds::SeedConst);
     off += (size_t)block * 8;
     off = round16(off + (size_t)block * 4);
     off = round16(off + (size_t)icap * 4);
-    return round16(off + (size_t)icap * 8) + ds::kept_lds_bytes(tcap);
+    L.kept = round16(off + (size_t)icap * 8);
+    L.total = L.kept + ds::kept_lds_bytes(tcap);
+    return L;
 }
 
-// k_vertex: the event's kept tracks, then the survivor ring of the pair loop
+// k_vertex: the event's kept tracks, their row table, then the survivor ring of the pair loop
 size_t vertex_lds(int tcap, int block)
 {
-    return ds::kept_lds_bytes(tcap) + sizeof(int) * (size_t)ds::vtx_ring_ints(block);
+    return ds::kept_lds_bytes(tcap) + ds::kept_rows_bytes(tcap) + sizeof(int) * (size_t)ds::vtx_ring_ints(block);
 }
 
 int round_up(int v, int m) { return ((v + m - 1) / m) * m; }
@@ -345,13 +359,25 @@ ds_status plan_track(ds_ctx *c, const ds_events *ev, const ds_tracks *out, int f
     const int icap = std::max(block * ITEMS_PER_SEED, ds::MAX_L3);
     const int tcap = vertex_fused ? round_up(std::max(ev->max_seeds_per_event, 1), 16) : 0;
     if (tcap > 32767) return DS_E_CAPACITY;   // 15-bit kept-track indices
-    size_t lds = track_lds(hcap, nb, nb3, block, icap, tcap);
-    if (lds > LDS_LIMIT) return DS_E_CAPACITY;
+    const TrackLayout L = track_layout(hcap, nb, nb3, block, icap, tcap);
+    size_t lds = L.total;
     // the network's feature tiles reuse the seed-constant ... item region
-    if (track_lds(0, 0, 0, block, icap, 0) - 16 < (size_t)(block / 64) * ds::MLP_TILE * 4) return DS_E_CAPACITY;
-    // ... and so does the fused pair loop's survivor ring
-    if (vertex_fused && track_lds(0, 0, 0, block, icap, 0) - 16 < sizeof(int) * (size_t)ds::vtx_ring_ints(block))
-        return DS_E_CAPACITY;
+    const size_t region = L.kept - L.sc;
+    if (region < (size_t)(block / 64) * ds::MLP_TILE * 4) return DS_E_CAPACITY;
+    // ... and so do the fused pair loop's survivor ring and, where it fits
+    // after the ring, the kept tracks' row table (else it gets its own space)
+    int krow_off = 0;
+    if (vertex_fused) {
+        const size_t ring = round16(sizeof(int) * (size_t)ds::vtx_ring_ints(block));
+        if (region < ring) return DS_E_CAPACITY;
+        if (region - ring >= ds::kept_rows_bytes(tcap)) {
+            krow_off = (int)(L.sc + ring);
+        } else {
+            krow_off = (int)lds;
+            lds += ds::kept_rows_bytes(tcap);
+        }
+    }
+    if (lds > LDS_LIMIT) return DS_E_CAPACITY;
     ds::TrackArgs &a = p->a;
     std::memset(&a, 0, sizeof(a));
     a.n_events = ev->n_events;
@@ -388,6 +414,7 @@ ds_status plan_track(ds_ctx *c, const ds_events *ev, const ds_tracks *out, int f
     a.hcap = hcap;
     a.icap = icap;
     a.tcap = tcap;
+    a.krow_off = krow_off;
     a.nb = nb;
     a.nbu = nbu;
     a.u0 = (float)c->u_min;

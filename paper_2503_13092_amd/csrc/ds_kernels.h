@@ -112,6 +112,7 @@ struct TrackArgs {
     float *r_x, *r_y, *r_tx, *r_ty, *r_qop, *r_chi2, *r_score;
     // fused vertexing (ds_process): kept tracks of an event go to LDS as they are written
     int tcap;            // LDS capacity for kept tracks of one event
+    int krow_off;        // fused vertexing: byte offset in LDS of the row starts and descriptors (kept_rows_bytes)
     float score_max;
     int vcap;
     int *vcount, *vi, *vj;
@@ -1262,11 +1263,13 @@ constexpr int vtx_ring() { return vtx_ring_ints(BLOCK); }
 
 // Kept tracks of one event in LDS, the vertexing input.  Positive-charge
 // tracks fill st/q/slot from the front and negative ones from the back, each
-// list in slot order (the o-th negative at tcap - 1 - o).  row[r] describes
-// the r-th kept track in slot order: its index o in its charge list, | 0x8000
-// when positive; the tracks of the other charge before it number r - o, so
-// its partners of higher slot are that list's entries from r - o on.  R[r] is
-// the rank of row r's first pair (R[n] = all pairs), filled by the vertexing.
+// list in slot order (the o-th negative at tcap - 1 - o).  The vertexing
+// derives the row table from them: row[r] describes the r-th kept track in
+// slot order (its index o in its charge list, | 0x8000 when positive; the
+// tracks of the other charge before it number r - o, so its partners of
+// higher slot are that list's entries from r - o on), and R[r] is the rank of
+// row r's first pair (R[n] = all pairs).  The table lives apart from the list
+// (in the fused kernel, on buffers that are dead by then).
 struct Kept {
     float4 *st;      // x, y, tx, ty at the UT midpoint
     float *q;        // fitted q/p
@@ -1277,17 +1280,22 @@ struct Kept {
 
 __host__ __device__ constexpr size_t kept_lds_bytes(int tcap)
 {
-    return tcap > 0 ? ((size_t)tcap * 30 + 4 + 15) & ~(size_t)15 : 0;
+    return tcap > 0 ? ((size_t)tcap * 24 + 15) & ~(size_t)15 : 0;
 }
 
-__device__ __forceinline__ Kept kept_carve(unsigned char *base, int tcap)
+__host__ __device__ constexpr size_t kept_rows_bytes(int tcap)
+{
+    return tcap > 0 ? ((size_t)tcap * 6 + 4 + 15) & ~(size_t)15 : 0;
+}
+
+__device__ __forceinline__ Kept kept_carve(unsigned char *base, unsigned char *rows, int tcap)
 {
     Kept k;
     k.st = reinterpret_cast<float4 *>(base);
     k.q = reinterpret_cast<float *>(base + (size_t)tcap * 16);
     k.slot = reinterpret_cast<int *>(base + (size_t)tcap * 20);
-    k.R = reinterpret_cast<int *>(base + (size_t)tcap * 24);
-    k.row = reinterpret_cast<uint16_t *>(base + (size_t)tcap * 28 + 4);
+    k.R = reinterpret_cast<int *>(rows);
+    k.row = reinterpret_cast<uint16_t *>(rows + (size_t)tcap * 4 + 4);
     return k;
 }
 
@@ -1303,15 +1311,23 @@ __device__ __forceinline__ void kept_append(const Kept &K, int tcap, bool kept, 
     if (kept) {
         const int r = n + (ex & 0xffff);
         const int pb = np + (ex >> 16);   // positive tracks before this one
-        const int o = positive ? pb : r - pb;
-        const int pos = positive ? o : tcap - 1 - o;
+        const int pos = positive ? pb : tcap - 1 - (r - pb);
         K.st[pos] = st;
         K.q[pos] = q;
         K.slot[pos] = (slot << 1) | (positive ? 1 : 0);
-        K.row[r] = (uint16_t)(o | (positive ? 0x8000 : 0));
     }
     n += tot & 0xffff;
     np += tot >> 16;
+}
+
+// Number of entries of a charge list (m of them, slot order) with a slot
+// below sl: the list's i-th slot is at K.slot[b + d * i].
+__device__ __forceinline__ int slots_below(const Kept &K, int b, int d, int m, int sl)
+{
+    int lo = 0;
+    for (int step = m > 0 ? 1 << (31 - __builtin_clz(m)) : 0; step > 0; step >>= 1)
+        if (lo + step <= m && (K.slot[b + d * (lo + step - 1)] >> 1) < sl) lo += step;
+    return lo;
 }
 
 __device__ __forceinline__ bool pair_prescreen(const DevGeom &G, float4 A, float4 B)
@@ -1337,9 +1353,22 @@ __device__ __forceinline__ void vertex_event_block(const Args &a, const DevGeom 
     const int tid = threadIdx.x;
     const bool curved = (G.fp != 0.0);
     const int nn = n - np;   // negative tracks
-    // row starts: row r pairs with the other charge list's entries from r - o on
+    // row table: each track's rank in slot order (its index in its list plus
+    // the tracks of the other list with a lower slot), then the row starts;
+    // row r pairs with the other list's entries from r - o on
     int npairs = 0;
     if (np > 0 && nn > 0) {
+        for (int e0 = 0; e0 < n; e0 += BLOCK) {
+            const int e = e0 + tid;
+            if (e < n) {
+                const bool pos = e < np;
+                const int o = pos ? e : e - np;
+                const int sl = K.slot[pos ? o : tcap - 1 - o] >> 1;
+                const int r = o + (pos ? slots_below(K, tcap - 1, -1, nn, sl) : slots_below(K, 0, 1, np, sl));
+                K.row[r] = (uint16_t)(o | (pos ? 0x8000 : 0));
+            }
+        }
+        lds_barrier();
         for (int r0 = 0; r0 < n; r0 += BLOCK) {
             const int r = r0 + tid;
             int len = 0;
@@ -1914,7 +1943,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2
                 // kept tracks appended in slot order, split by seed charge
                 int nk = s_nkept, nkp = s_nkpos;
                 const int tcap = kernel_args<TrackKernArgs>().a.tcap;
-                kept_append<BLOCK>(kept_carve(smem + kept_off, tcap), tcap, kept, sd.qop > 0.0f, make_float4(t.x, t.y, t.tx, t.ty), t.qop, i - s0,
+                // (appending writes the list only: the row table is built by the vertexing)
+                kept_append<BLOCK>(kept_carve(smem + kept_off, smem + kept_off, tcap), tcap, kept, sd.qop > 0.0f,
+                                   make_float4(t.x, t.y, t.tx, t.ty), t.qop, i - s0,
                                    nk, nkp, s_wsum);
                 lds_barrier();
                 if (tid == 0) {
@@ -1927,8 +1958,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2
         }
         if (VTX) {
             const TrackKernArgs &Kv = kernel_args<TrackKernArgs>();
-            vertex_event_block<BLOCK, XTR>(Kv.a, Kv.G, e, s0, s_nkept, s_nkpos, kept_carve(smem + kept_off, Kv.a.tcap),
-                                           Kv.a.tcap, reinterpret_cast<int *>(s_c), s_wsum);
+            vertex_event_block<BLOCK, XTR>(Kv.a, Kv.G, e, s0, s_nkept, s_nkpos,
+                                           kept_carve(smem + kept_off, smem + Kv.a.krow_off, Kv.a.tcap), Kv.a.tcap,
+                                           reinterpret_cast<int *>(s_c), s_wsum);
         }
     }
     const TrackArgs &a = kernel_args<TrackKernArgs>().a;
@@ -2246,13 +2278,14 @@ __device__ __forceinline__ void wave_sync()
 // Standalone vertexing (ds_vertex): a workgroup per event (work-stolen); the
 // event's kept tracks (nhits > 0, score < score_max) are compacted into LDS in
 // slot order, then the pairs go through vertex_event_block, the routine of the
-// fused step.  LDS: kept tracks (kept_lds_bytes(tcap)) and the survivor ring.
+// fused step.  LDS: kept tracks (kept_lds_bytes), their row table
+// (kept_rows_bytes) and the survivor ring.
 template <int BLOCK, bool XTR>
 __global__ __launch_bounds__(BLOCK) void k_vertex(VertexArgs a, DevGeom G)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const Kept K = kept_carve(smem, a.tcap);
-    int *ring = reinterpret_cast<int *>(smem + kept_lds_bytes(a.tcap));
+    const Kept K = kept_carve(smem, smem + kept_lds_bytes(a.tcap), a.tcap);
+    int *ring = reinterpret_cast<int *>(smem + kept_lds_bytes(a.tcap) + kept_rows_bytes(a.tcap));
     __shared__ int s_e;
     __shared__ int s_wsum[BLOCK / 64];
     const int tid = threadIdx.x;
