@@ -185,6 +185,7 @@ def main():
                     help="per launch; default: read from the benchmark JSON line in <dir>/prof_bench.json")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--config", type=int, default=1)
+    ap.add_argument("--workload", default=None, help="workload text (default: the benchmark line's)")
     args = ap.parse_args()
     if args.print_commands:
         for k, c in commands(args.steps, args.config).items():
@@ -201,7 +202,7 @@ def main():
         line = [l for l in open(bj) if l.startswith("{")][-1]
         b = json.loads(line)
         ab = ab or b["roofline"]["algorithmic_bytes_per_launch"]
-        workload = b["config"]["workload"]
+        workload = args.workload or b["config"]["workload"]
         src = b.get("kernel_source")     # the source the profiled run was built from
     if ab is None:
         raise SystemExit("algorithmic bytes unknown: pass --algorithmic-bytes or provide prof_bench.json")
