@@ -342,6 +342,52 @@ def test_fused_process_graph_matches_oracle(ctx, config, n, cap):
     assert vc["n_ref"] + ref["vertices"]["overflow"] > (1000 if config == 4 else 0)
 
 
+def test_fused_vertexing_of_large_events_matches_oracle():
+    """Events of 2 600 seeds with every found track vertexed (about 2 500
+    kept tracks, about 1.5 M opposite-charge pairs and 50 000 vertices per
+    event).
+    At 256 lanes the fused step's row table (6 bytes per kept-track slot) no
+    longer fits on the tracking kernel's dead buffers and takes LDS of its
+    own; at 512 lanes it fits there.  Both, and the two-launch step (the
+    standalone vertexing kernel, with its own LDS layout), match the oracle
+    and each other bitwise."""
+    cfg = dict(name="wide", n_events=3, seed=23, seeds_per_event=2600, llp_per_event=600, hits_per_layer=300,
+               zmax=2200.0)
+    b = synth.generate(cfg)
+    cap = 65536
+    say(f"[parity] large events: {b.n_seeds} seeds, {b.n_hits} hits")
+    ref = O.run_path(b, G0, W, score_max=math.inf, cap=cap, n_threads=8)
+    c = ds.Context(0, G0, W)
+    outs = []
+    try:
+        for block, fused in ((256, 1), (512, 1), (256, 0)):
+            ds.ds_set_launch(c.handle, 0, block, 1, 1024)
+            ds.ds_set_step_fusion(c.handle, fused)
+            say(f"[parity] large events: block {block}, fused {fused}")
+            ev = ds.DeviceEvents(b)
+            tr = ds.DeviceTracks(b.n_seeds)
+            vt = ds.DeviceVertices(b.n_events, cap)
+            ds.ds_process(c.handle, ev, tr, vt, ds.DS_MODE_PERSISTENT, score_max=math.inf)
+            torch.cuda.synchronize()
+            outs.append((tr.to_numpy(), vt.to_numpy()))
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+    gt, gv = outs[0]
+    assert gt["flags"] == 0 and gv["flags"] == 0
+    tc = parity.compare_tracks(gt, ref["tracks"])
+    found = ref["tracks"]["nhits"] > 0
+    sc = parity.compare_scores(gt["score"], ref["score"], found & (gt["nhits"] == ref["tracks"]["nhits"]))
+    vc = parity.compare_vertices(gv, ref["vertices"], G0["doca_max"], parity.excused_slot_set(b, tc, sc))
+    assert vc["n_ref"] > 100000 and ref["vertices"]["overflow"] == 0
+    for ot, ov in outs[1:]:
+        for k in ("count", "i", "j", "x", "y", "z", "doca"):
+            assert np.array_equal(ov[k], gv[k]), k
+        for k in ("x", "y", "tx", "ty", "qop", "chi2", "score", "nhits"):
+            assert np.array_equal(ot[k], gt[k]), k
+    say(f"[parity] large events: identical {tc['identical']}/{tc['n']}, vertices {vc['n_gpu']}/{vc['n_ref']}")
+
+
 def test_largest_first_order_matches_oracle_and_input_order():
     """Largest-first event order (two sorting launches ahead of the
     persistent launch): on uneven events every event is processed exactly
