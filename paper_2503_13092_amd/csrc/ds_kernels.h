@@ -1070,20 +1070,20 @@ template <bool DV1, int HPT>
 __device__ __forceinline__ void load_round(const TrackArgs &a, int base, int n, int r, float u[HPT],
                                            uint32_t sp[HPT / 4])
 {
+    // one lane pointer and constant offsets (64 j elements): no per-slot
+    // address registers to keep; slot j is in the run iff lane < n - r 64 HPT - 64 j
     const int lane = threadIdx.x & 63;
+    const int lim = n - r * 64 * HPT;
+    const float *hp = a.hu + base + r * 64 * HPT + lane;
 #pragma unroll
-    for (int j = 0; j < HPT; ++j) {
-        const int k = r * 64 * HPT + lane + 64 * j;
-        u[j] = (k < n) ? a.hu[base + k] : 0.0f;
-    }
+    for (int j = 0; j < HPT; ++j) u[j] = (lane < lim - 64 * j) ? hp[64 * j] : 0.0f;
     if (DV1) {
+        const uint8_t *sp8 = a.hsec + base + r * 64 * HPT + lane;
 #pragma unroll
         for (int q = 0; q < HPT / 4; ++q) sp[q] = 0u;
 #pragma unroll
-        for (int j = 0; j < HPT; ++j) {
-            const int k = r * 64 * HPT + lane + 64 * j;
-            if (k < n) sp[j >> 2] |= (uint32_t)a.hsec[base + k] << (8 * (j & 3));
-        }
+        for (int j = 0; j < HPT; ++j)
+            if (lane < lim - 64 * j) sp[j >> 2] |= (uint32_t)sp8[64 * j] << (8 * (j & 3));
     }
 }
 
