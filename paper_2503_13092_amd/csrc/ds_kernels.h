@@ -1593,17 +1593,20 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(CANDS ? 2
         int hl[4];
 #pragma unroll
         for (int L = 0; L < 4; ++L) hl[L] = ho[L] - ho[0];
-        // seed frames of the first chunk, computed while the hits are loading
+        // seed frames of the first chunk, computed while the hits are loading;
+        // the seeds are loaded first, so that the frames wait for them alone
+        const bool have0 = tid < s1 - s0;
+        SeedRaw sd0{};
+        if (have0) sd0 = load_seed(a, s0 + tid);
         auto first_frames = [&]() {
-            if (tid < s1 - s0) {
-                const int i = s0 + tid;
+            if (have0) {
                 SeedConst sc;
                 double m3, W1;
-                if (!seed_frame(G, a.sx[i], a.sy[i], a.stx[i], a.sty[i], a.sqop[i], sc, m3, W1)) {
+                if (!seed_frame(G, sd0.x, sd0.y, sd0.tx, sd0.ty, sd0.qop, sc, m3, W1)) {
                     atomicOr(a.flags, F_NONFINITE);
                     sc.q = __int_as_float(0x7fc00000);   // NaN: no frame
                 } else if (DV1) {
-                    seed_sectors(G, a.sy[i], a.sty[i], sc);
+                    seed_sectors(G, sd0.y, sd0.ty, sc);
                 }
                 s_c[tid] = sc;
             }
