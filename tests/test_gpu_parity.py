@@ -647,6 +647,37 @@ def test_launch_shapes_bitwise_equal(algorithm):
         c.close()
 
 
+def test_vertex_launch_shapes_bitwise_equal():
+    """The standalone vertexing launch (ds_vertex; the second launch of an
+    unfused step) at the workgroup sizes and counts the autotuner picks from:
+    the pair chunks, the survivor ring and the fit batches change with the
+    workgroup size, the vertices never do.  Stress occupancy, every found
+    track kept."""
+    b = synth.generate(4, n_events=24, seed=61)
+    c = ds.Context(0, G0, W)
+    try:
+        ev = ds.DeviceEvents(b)
+        tr = ds.DeviceTracks(b.n_seeds)
+        ds.ds_find_tracks(c.handle, ev, tr, ds.DS_MODE_PERSISTENT, 1)
+        torch.cuda.synchronize()
+        outs = []
+        for block, wpc in ((256, 4), (64, 16), (128, 8), (512, 2), (256, 5)):
+            say(f"[parity] vertex launch shape: block {block}, {wpc} per CU")
+            ds.ds_set_launch(c.handle, 1, block, wpc, 0)
+            vt = ds.DeviceVertices(b.n_events, 2048)
+            ds.ds_vertex(c.handle, ev, tr, math.inf, vt, ds.DS_MODE_GRAPH)
+            torch.cuda.synchronize()
+            outs.append(vt.to_numpy())
+        v0 = outs[0]
+        assert v0["flags"] == 0 and v0["count"].sum() > 5000
+        for v in outs[1:]:
+            for k in ("count", "i", "j", "x", "y", "z", "doca", "overflow"):
+                assert np.array_equal(v[k], v0[k]), k
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+
+
 @pytest.mark.parametrize("algorithm", [0, 1])
 def test_fused_step_masses_and_lines_match_standalone(algorithm):
     """ds_process with masses and trigger-line outputs (the fused launch's
