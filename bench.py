@@ -166,6 +166,77 @@ def launch_settings(ds, ctx):
                 vertex_launch=dict(zip(("block", "wg_per_cu"), ds.ds_get_launch(ctx, 1)[:2])))
 
 
+def _timed(torch, stream, fn, warmup, reps):
+    """Mean HIP-event time (ms) of fn on the launch stream, after warmup calls."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    pairs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(reps)]
+    for p in pairs:
+        p[0].record(stream)
+        fn()
+        p[1].record(stream)
+    torch.cuda.synchronize()
+    return float(np.mean([p[0].elapsed_time(p[1]) for p in pairs]))
+
+
+def next_rows(ds, autotune, torch, g, w, batch, copies, mode, score_max, stream, warmup, reps):
+    """The rows after the hot path, each on the same batch and launch mode:
+    clone killing (the step with geometry clone_kill set: tracking, then the
+    clone-killing and ghost-killer launches, then vertexing), every enumerated
+    candidate scored (ds_score_candidates: one row per candidate, cleared and
+    written every call), and the vertices' masses and trigger-line scores
+    (ds_process with the extras outputs: the fused launch's extras
+    instantiation)."""
+    E = batch.n_events
+    ev, tr, vt = copies[0]
+    out = {}
+    # clone killing
+    ctx = ds.Context(0, dict(g, clone_kill=1), w)
+    autotune.apply_cached(ctx.handle, batch, 0)
+    ms = _timed(torch, stream, lambda: ds.ds_process(ctx.handle, ev, tr, vt, mode, score_max=score_max, stream=stream),
+                warmup, reps)
+    nh = tr.nhits.cpu().numpy()
+    out["clone_killing"] = dict(ms_per_step=round(ms, 4), events_per_s=round(E / (ms * 1e-3), 1),
+                                tracks=int(np.sum(nh > 0)), flags=int(tr.flags.item()) | int(vt.flags.item()),
+                                launch="ds_process with clone_kill: tracking, clone-killing, ghost-killer and "
+                                       "vertexing launches, hipGraph replay")
+    ctx.close()
+    # every candidate scored (a 56-byte row per valid candidate; every slot's nhits cleared first)
+    ctx = ds.Context(0, g, w)
+    slots = ds.ds_candidate_slots(ctx.handle)
+    cd = ds.DeviceCandidates(batch.n_seeds, slots)
+    ms = _timed(torch, stream, lambda: ds.ds_score_candidates(ctx.handle, ev, cd, stream=stream), warmup, reps)
+    rows = int(np.sum(cd.nhits.cpu().numpy() > 0))
+    written = 4.0 * batch.n_seeds * slots + 56.0 * rows
+    out["all_candidates_scored"] = dict(ms=round(ms, 4), candidates=rows, slots_per_seed=slots,
+                                        candidates_per_s=round(rows / (ms * 1e-3), 1),
+                                        bytes_written_per_call=round(written),
+                                        write_GBs=round(written / (ms * 1e-3) / 1e9, 1))
+    del cd
+    ctx.close()
+    # masses and trigger lines after vertexing
+    ctx = ds.Context(0, g, w)
+    autotune.apply_cached(ctx.handle, batch, 0)
+    ds.ds_load_lines(ctx.handle, synth_line_weights())
+    vx = ds.DeviceVertices(batch.n_events, vt.cap, extras=True)
+    ms = _timed(torch, stream, lambda: ds.ds_process(ctx.handle, ev, tr, vx, mode, score_max=score_max, stream=stream),
+                warmup, reps)
+    out["masses_and_lines"] = dict(ms_per_step=round(ms, 4), events_per_s=round(E / (ms * 1e-3), 1),
+                                   vertices=int(vx.count.sum().item()),
+                                   flags=int(tr.flags.item()) | int(vx.flags.item()),
+                                   launch="ds_process with masses and trigger-line outputs (the extras "
+                                          "instantiation of the fused launch), hipGraph replay")
+    del vx
+    ctx.close()
+    return out
+
+
+def synth_line_weights():
+    from paper_2503_13092_amd import synth
+    return synth.line_weights()
+
+
 def copy_ceiling_gbs(torch, nbytes=2 << 30, reps=10):
     """Achievable HBM bandwidth of a plain device-to-device copy (read + write)."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -217,6 +288,8 @@ def main():
     ap.add_argument("--no-copy-ceiling", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-dv1", action="store_true", help="skip the Dv1 (triplet search) line")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the next rows (clone killing, every candidate scored, masses and trigger lines)")
     ap.add_argument("--serve-seconds", type=float, default=1.5)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -396,6 +469,9 @@ def main():
                           launch="ds_process, algorithm 1: one fused persistent launch, hipGraph replay",
                           launch_settings=launch_settings(ds, ctx1.handle), autotuned=tuned1 is not None)
         ctx1.close()
+    if not args.no_next:
+        out["next_rows"] = next_rows(ds, autotune, torch, g, w, batch, copies, mode, score_max, stream, args.warmup,
+                                     max(5, args.steps // 2))
     if not args.no_copy_ceiling:
         cc = copy_ceiling_gbs(torch)
         out["roofline"]["copy_ceiling_GBs"] = round(cc, 1)
