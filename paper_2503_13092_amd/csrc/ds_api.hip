@@ -102,6 +102,7 @@ struct ds_ctx {
     bool clone_kill = false;
     int algorithm = 0;             // 0: Dv0 window search, 1: Dv1 triplet search
     float *d_W = nullptr;    // ghost-killer weights, per-lane MFMA order (mlp_lane_layout)
+    float *d_Wrow = nullptr; // the same, row-major (the candidate rows' per-lane network)
     float *d_WL = nullptr;   // trigger-line networks
     int *d_counters = nullptr;  // [MAX_STREAM_SLOTS][4]
     std::map<void *, int> slots;
@@ -806,6 +807,7 @@ void ds_destroy(ds_ctx *c)
     (void)hipSetDevice(c->device);
     for (auto &g : c->graphs) release_graph(g.second);
     if (c->d_W) (void)hipFree(c->d_W);
+    if (c->d_Wrow) (void)hipFree(c->d_Wrow);
     if (c->d_WL) (void)hipFree(c->d_WL);
     if (c->d_counters) (void)hipFree(c->d_counters);
     for (auto &o : c->order_ws)
@@ -890,6 +892,9 @@ ds_status ds_load_geometry(ds_ctx *c, const ds_geometry *g, const float *w, size
     ds::mlp_lane_layout(w, wm.data());
     if (!c->d_W && hipMalloc(&c->d_W, sizeof(float) * ds::MLP_WM) != hipSuccess) return DS_E_NOMEM;
     if (hipMemcpy(c->d_W, wm.data(), sizeof(float) * ds::MLP_WM, hipMemcpyHostToDevice) != hipSuccess)
+        return DS_E_DEVICE;
+    if (!c->d_Wrow && hipMalloc(&c->d_Wrow, sizeof(float) * ds::NWEIGHTS) != hipSuccess) return DS_E_NOMEM;
+    if (hipMemcpy(c->d_Wrow, w, sizeof(float) * ds::NWEIGHTS, hipMemcpyHostToDevice) != hipSuccess)
         return DS_E_DEVICE;
     c->G = G;
     c->u_min = g->u_min;
@@ -1012,17 +1017,14 @@ ds_status ds_score_candidates(ds_ctx *c, const ds_events *ev, const ds_candidate
     p.a.r_qop = out->qop;
     p.a.r_chi2 = out->chi2;
     p.a.r_score = out->score;
+    p.a.Wrow = c->d_Wrow;   // each candidate is scored where it is written
     const long long rows = (long long)ev->n_seeds * cmax;
     if (rows > 0) {
         const int grid = (int)std::min<long long>((rows + 255) / 256, (long long)c->n_cu * 16);
         hipLaunchKernelGGL(ds::k_clear_rows, dim3(grid), dim3(256), 0, s, out->nhits, rows);
         if (hipGetLastError() != hipSuccess) return DS_E_DEVICE;
     }
-    hipError_t e = run_track(c, p, DS_MODE_PERSISTENT, s);
-    if (e != hipSuccess) return DS_E_DEVICE;
-    const int grid = std::max(1, std::min(ev->n_events, c->n_cu * 8));
-    hipLaunchKernelGGL(ds::k_score_rows, dim3(grid), dim3(256), 0, s, p.a, c->G);
-    return dev_err(hipGetLastError());
+    return dev_err(run_track(c, p, DS_MODE_PERSISTENT, s));
 }
 
 ds_status ds_vertex(ds_ctx *c, const ds_events *ev, const ds_tracks *trk, float score_max, const ds_vertices *out,

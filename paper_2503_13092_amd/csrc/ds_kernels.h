@@ -110,6 +110,7 @@ struct TrackArgs {
     int cmax;
     int *r_seed, *r_cand, *r_nhits, *r_h0, *r_h1, *r_h2, *r_h3;
     float *r_x, *r_y, *r_tx, *r_ty, *r_qop, *r_chi2, *r_score;
+    const float *Wrow;   // candidate rows: the ghost-killer weights W1, b1, W2, b2, W3, b3 row-major
     // fused vertexing (ds_process): kept tracks of an event go to LDS as they are written
     int tcap;            // LDS capacity for kept tracks of one event
     int krow_off;        // fused vertexing: byte offset in LDS of the row starts and descriptors (kept_rows_bytes)
@@ -384,6 +385,33 @@ __device__ __forceinline__ void ghost_features(const DevGeom &G, float xf, float
 // Read-only, wave-uniform parameters: loads through the constant address
 // space become scalar loads and the weights feed the FMAs as SGPR operands.
 typedef const __attribute__((address_space(4))) float cfloat;
+
+// The ghost-killer network of one lane on the vector ALUs, its weights read
+// through the scalar cache (the same for every lane): for rows produced one at
+// a time in divergent code, where the wavefront network cannot run.  Hidden
+// layer 1 is consumed as it is produced (h2 accumulates over it in unit order).
+__device__ __forceinline__ float mlp_score_lane(const float *Wg, const float f[NF])
+{
+    asm volatile("" : "+s"(Wg));   // keeps the weight loads beside their uses
+    cfloat *W1 = (cfloat *)(Wg), *b1 = W1 + NH1 * NF, *W2 = b1 + NH1, *b2 = W2 + NH2 * NH1, *W3 = b2 + NH2,
+           *b3 = W3 + NH2;
+    float h2[NH2];
+#pragma unroll
+    for (int k = 0; k < NH2; ++k) h2[k] = b2[k];
+#pragma unroll
+    for (int j = 0; j < NH1; ++j) {
+        float z = b1[j];
+#pragma unroll
+        for (int k = 0; k < NF; ++k) z = fmaf(W1[j * NF + k], f[k], z);
+        const float h = fmaxf(z, 0.0f);
+#pragma unroll
+        for (int k = 0; k < NH2; ++k) h2[k] = fmaf(W2[k * NH1 + j], h, h2[k]);
+    }
+    float z = b3[0];
+#pragma unroll
+    for (int k = 0; k < NH2; ++k) z = fmaf(W3[k], fmaxf(h2[k], 0.0f), z);
+    return 1.0f / (1.0f + __expf(-z));
+}
 
 // 17 -> 32 ReLU -> 16 ReLU -> 1 sigmoid, float32 FMA; W is wave-uniform.
 // The ghost-killer network ("Ghost-Killer Neural Network": 17 inputs, ReLU
@@ -1006,7 +1034,8 @@ __device__ __forceinline__ void write_candidate_row(const TrackArgs &a, const De
                                            double be, double c2, const float *hu_s, const uint16_t *hidx_s,
                                            const int bp[4])
 {
-    const StoredTrack t = stored_track(G, load_seed(a, i), n, al, be, c2, hu_s, bp, nullptr);
+    float f[NF];
+    const StoredTrack t = stored_track(G, load_seed(a, i), n, al, be, c2, hu_s, bp, f);
     const size_t r = (size_t)i * (size_t)a.cmax + (size_t)c;
     a.r_seed[r] = i;
     a.r_cand[r] = c;
@@ -1021,6 +1050,7 @@ __device__ __forceinline__ void write_candidate_row(const TrackArgs &a, const De
     a.r_ty[r] = t.ty;
     a.r_qop[r] = t.qop;
     a.r_chi2[r] = t.chi2;
+    a.r_score[r] = mlp_score_lane(a.Wrow, f);
 }
 
 // The launch's binning parameters, read once per event and held in scalar
@@ -2066,50 +2096,6 @@ __global__ void k_clear_rows(int *r_nhits, long long n)
 {
     for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long long)gridDim.x * blockDim.x)
         r_nhits[k] = 0;
-}
-
-// Ghost scores of the candidate rows: one workgroup per event, lane per row.
-__global__ __launch_bounds__(256) void k_score_rows(TrackArgs a, DevGeom G)
-{
-    for (int e = blockIdx.x; e < a.n_events; e += gridDim.x) {
-        const int s0 = a.seed_off[e], s1 = a.seed_off[e + 1];
-        int ho[5];
-#pragma unroll
-        for (int L = 0; L < 5; ++L) ho[L] = a.hit_off[4 * e + L];
-        bool ok = (0 <= s0) && (s0 <= s1) && (s1 <= a.n_seeds) && (0 <= ho[0]) && (ho[4] <= a.n_hits);
-#pragma unroll
-        for (int L = 0; L < 4; ++L) ok = ok && (ho[L] <= ho[L + 1]);
-        if (!ok) continue;
-        const long long r0 = (long long)s0 * a.cmax, r1 = (long long)s1 * a.cmax;
-        // uniform trip count: the network runs on whole wavefronts
-        for (long long rb = r0; rb < r1; rb += blockDim.x) {
-            const long long r = rb + threadIdx.x;
-            const int nh = r < r1 ? a.r_nhits[r] : 0;
-            float f[NF];
-            if (nh > 0) {
-                const int i = (int)(r / a.cmax);
-                const int hh[4] = {a.r_h0[r], a.r_h1[r], a.r_h2[r], a.r_h3[r]};
-                float hu4[4];
-                int has = 0;
-#pragma unroll
-                for (int L = 0; L < 4; ++L) {
-                    hu4[L] = 0.0f;
-                    if (hh[L] >= 0 && hh[L] < ho[L + 1] - ho[L]) {
-                        hu4[L] = a.hu[ho[L] + hh[L]];
-                        has |= 1 << L;
-                    }
-                }
-                ghost_features(G, a.r_x[r], a.r_y[r], a.r_tx[r], a.r_ty[r], a.r_qop[r], a.r_chi2[r], nh, a.sx[i],
-                               a.sy[i], a.stx[i], a.sty[i], a.sqop[i], hu4, has, f);
-            }
-            if (__ballot(nh > 0) != 0) {
-                float mw[MLP_LANE_WORDS];
-                mlp_lane_weights(a.W, mw);
-                const float sc = mlp_score_wave(mw, f, nh > 0);
-                if (nh > 0) a.r_score[r] = sc;
-            }
-        }
-    }
 }
 
 // Standalone ghost-killer: one workgroup per event (grid-stride), lane per seed.
